@@ -1,0 +1,182 @@
+"""FP64 CPU oracle (test infrastructure).
+
+Plain double-precision loops over the definitions of the star and box stencil
+sweeps (Sec. I problem statement, Sec. II-A high-order case) and of the acoustic
+wave step, its exact adjoint and the gradient with respect to C^2 = (v dt/h)^2.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It shares no code with the HIP library:
+the C source next to this file is compiled with gcc on its own and loaded
+through ctypes.  Inputs arrive as the same FP32 values the GPU gets, promoted to
+FP64, so a comparison measures kernel arithmetic and not input rounding.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mms_oracle.c")
+_LIB = os.path.join(_HERE, "libmms_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc -O2 (no fast-math) and OpenMP."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_long), ("ny", ctypes.c_long), ("nz", ctypes.c_long),
+                ("H", ctypes.c_long), ("sy", ctypes.c_long), ("sz", ctypes.c_long)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _Wave(ctypes.Structure):
+    _fields_ = [("g", _Grid), ("r", ctypes.c_int), ("lap", _dp), ("c2", _dp),
+                ("sponge_width", ctypes.c_int), ("sponge_alpha", ctypes.c_double),
+                ("sponge_faces", ctypes.c_int), ("src_z", ctypes.c_long),
+                ("src_y", ctypes.c_long), ("src_x", ctypes.c_long), ("src", _dp),
+                ("nt", ctypes.c_int)]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        gp = ctypes.POINTER(_Grid)
+        wp = ctypes.POINTER(_Wave)
+        lib.orc_star.argtypes = [_dp, _dp, gp, ctypes.c_int, _dp]
+        lib.orc_box.argtypes = [_dp, _dp, gp, ctypes.c_int, _dp]
+        lib.orc_sponge_1d.argtypes = [ctypes.c_long, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, _dp]
+        lib.orc_wave_step.argtypes = [wp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_wave_forward.argtypes = [wp, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_adjoint_step.argtypes = [wp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_wave_adjoint.argtypes = [wp, _dp, _dp, _dp, _dp, _dp, _dp]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _grid(a: np.ndarray, nx: int, ny: int, nz: int, halo: int) -> _Grid:
+    assert a.ndim == 3 and a.shape[0] == nz + 2 * halo and a.shape[1] == ny + 2 * halo
+    assert a.shape[2] >= nx + 2 * halo
+    return _Grid(nx, ny, nz, halo, a.shape[2], a.shape[1] * a.shape[2])
+
+
+def star(inp: np.ndarray, nx: int, ny: int, nz: int, radius: int, coeffs,
+         halo: int = 4) -> np.ndarray:
+    """Star sweep of a padded grid; coeffs [3][2r+1] (axis z, y, x).  Returns padded FP64."""
+    a = _f64(inp)
+    out = np.zeros_like(a)
+    c = _f64(np.asarray(coeffs).reshape(3, 2 * radius + 1))
+    g = _grid(a, nx, ny, nz, halo)
+    _load().orc_star(_ptr(a), _ptr(out), ctypes.byref(g), radius, _ptr(c))
+    return out
+
+
+def box(inp: np.ndarray, nx: int, ny: int, nz: int, radius: int, coeffs,
+        halo: int = 4) -> np.ndarray:
+    """Box sweep of a padded grid; coeffs [dz][dy][dx].  Returns padded FP64."""
+    a = _f64(inp)
+    out = np.zeros_like(a)
+    n = 2 * radius + 1
+    c = _f64(np.asarray(coeffs).reshape(n, n, n))
+    g = _grid(a, nx, ny, nz, halo)
+    _load().orc_box(_ptr(a), _ptr(out), ctypes.byref(g), radius, _ptr(c))
+    return out
+
+
+def sponge_1d(n: int, width: int, alpha: float, damp_lo: bool, damp_hi: bool) -> np.ndarray:
+    g = np.zeros(n, dtype=np.float64)
+    _load().orc_sponge_1d(n, width, alpha, int(damp_lo), int(damp_hi), _ptr(g))
+    return g
+
+
+class Wave:
+    """Acoustic problem description for the oracle (all arrays promoted to FP64)."""
+
+    def __init__(self, nx, ny, nz, c2, lap_half, src, src_dt2f, nt, sponge_width=0,
+                 sponge_alpha=0.0, sponge_faces=0, halo=4):
+        self.nx, self.ny, self.nz, self.halo = nx, ny, nz, halo
+        self.c2 = _f64(c2)
+        self.lap = _f64(lap_half)
+        self.src_dt2f = _f64(src_dt2f)
+        self.shape = self.c2.shape
+        self.nt = nt
+        g = _grid(self.c2, nx, ny, nz, halo)
+        self._s = _Wave(g, len(lap_half) - 1, _ptr(self.lap), _ptr(self.c2), sponge_width,
+                        sponge_alpha, sponge_faces, src[0], src[1], src[2],
+                        _ptr(self.src_dt2f), nt)
+
+    @classmethod
+    def from_setup(cls, s, lap_half, nt=None):
+        return cls(s.nx, s.ny, s.nz, s.c2, lap_half, s.src, s.src_dt2f,
+                   s.nt if nt is None else nt, s.sponge_width, s.sponge_alpha, s.sponge_faces)
+
+    def zeros(self):
+        return np.zeros(self.shape, dtype=np.float64)
+
+    def step(self, n, uprev, ucur, image=None):
+        """u^{n+1} from (u^{n-1}, u^n); returns (u^{n+1}, d^n)."""
+        up, uc = _f64(uprev), _f64(ucur)
+        un = self.zeros()
+        tr = np.zeros((self.ny, self.nx))
+        _load().orc_wave_step(ctypes.byref(self._s), n, _ptr(up), _ptr(uc), _ptr(un),
+                              _ptr(tr), _ptr(image))
+        return un, tr
+
+    def forward(self, u0, u1, keep_states=False, image=False):
+        """Returns dict(traces [nt][ny][nx], last (u^{nt-1}, u^nt), states?, image?)."""
+        a, b = _f64(u0), _f64(u1)
+        tr = np.zeros((self.nt, self.ny, self.nx))
+        states = np.zeros((self.nt + 1,) + self.shape) if keep_states else None
+        last = np.zeros((2,) + self.shape)
+        img = self.zeros() if image else None
+        _load().orc_wave_forward(ctypes.byref(self._s), _ptr(a), _ptr(b), _ptr(tr),
+                                 _ptr(states), _ptr(last), _ptr(img))
+        return {"traces": tr, "last": last, "states": states, "image": img}
+
+    def adjoint_step(self, n, lam2, lam1, resid_n, u_n, grad):
+        """lam^n from (lam^{n+2}, lam^{n+1}); adds the step's term to grad in place."""
+        l2, l1 = _f64(lam2), _f64(lam1)
+        l0 = self.zeros()
+        r = None if resid_n is None else _f64(resid_n)
+        u = None if u_n is None else _f64(u_n)
+        assert grad is None or (grad.dtype == np.float64 and grad.flags.c_contiguous)
+        _load().orc_adjoint_step(ctypes.byref(self._s), n, _ptr(l2), _ptr(l1), _ptr(l0),
+                                 _ptr(r), _ptr(u), _ptr(grad))
+        return l0
+
+    def adjoint(self, states, resid):
+        """Full adjoint over stored states; returns (grad_c2, dJ/du0, dJ/du1, dJ/dsrc)."""
+        st = _f64(states)
+        rs = _f64(resid)
+        assert st.shape[0] >= self.nt and rs.shape == (self.nt, self.ny, self.nx)
+        g, l0, l1 = self.zeros(), self.zeros(), self.zeros()
+        gs = np.zeros(self.nt)
+        _load().orc_wave_adjoint(ctypes.byref(self._s), _ptr(st), _ptr(rs), _ptr(g), _ptr(l0),
+                                 _ptr(l1), _ptr(gs))
+        return g, l0, l1, gs

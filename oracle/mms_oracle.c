@@ -1,0 +1,307 @@
+/*
+ * FP64 CPU oracle for the high-order stencil sweep and the acoustic wave step
+ * it drives (MMStencil, arXiv 2507.11067).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain definition that the
+ * HIP library is checked against.  It shares no code, header or table with the
+ * library; only the test suite, the smoke check and the benchmark's CPU
+ * baseline load it.
+ *
+ * Every routine is a direct loop over the definition, in double precision,
+ * with OpenMP only over the outermost (z) loop of a sweep.  Grids use the
+ * padded layout: interior point (z, y, x) sits at element
+ *   (z + H) * sz + (y + H) * sy + (x + H)
+ * and the halo cells are read as stored (zero for the workloads).
+ *
+ * Passages followed:
+ *  - star and box stencils: the problem statement of Sec. I (star reaches
+ *    neighbours along the axes only, box reaches the whole (2r+1)^d cube) and
+ *    the radius-4 / 8th-order high-order case of Sec. II-A;
+ *  - the acoustic time step: the second-order-in-time wave update that RTM
+ *    (Sec. II-A, Sec. V-F) is built on, u^{n+1} = 2u^n - u^{n-1} + v^2 dt^2 L u^n
+ *    + source, with the damping sponge, source and receiver reading listed in
+ *    the design notes;
+ *  - the adjoint step and the gradient: the exact transpose of that recurrence
+ *    (derived in the design notes; the paper has no adjoint).
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+    long nx, ny, nz; /* interior extent */
+    long H;          /* halo width */
+    long sy, sz;     /* element strides of y and z; x stride is 1 */
+} orc_grid;
+
+static inline long at(const orc_grid *g, long z, long y, long x) {
+    return (z + g->H) * g->sz + (y + g->H) * g->sy + (x + g->H);
+}
+
+/* Star stencil, plain definition.
+ * out(p) = sum_{a in z,y,x} sum_{k=-r..r} c[a][k+r] * in(p + k e_a)
+ * c is [3][2r+1]: axis z first, then y, then x. */
+void orc_star(const double *in, double *out, const orc_grid *g, int r, const double *c) {
+    const int w = 2 * r + 1;
+    const double *cz = c, *cy = c + w, *cx = c + 2 * w;
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) {
+                double s = 0.0;
+                for (int k = -r; k <= r; ++k) s += cz[k + r] * in[at(g, z + k, y, x)];
+                for (int k = -r; k <= r; ++k) s += cy[k + r] * in[at(g, z, y + k, x)];
+                for (int k = -r; k <= r; ++k) s += cx[k + r] * in[at(g, z, y, x + k)];
+                out[at(g, z, y, x)] = s;
+            }
+}
+
+/* Box stencil, plain definition.
+ * out(p) = sum_{dz,dy,dx in [-r,r]} c[dz+r][dy+r][dx+r] * in(p + (dz,dy,dx)) */
+void orc_box(const double *in, double *out, const orc_grid *g, int r, const double *c) {
+    const int w = 2 * r + 1;
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) {
+                double s = 0.0;
+                for (int dz = -r; dz <= r; ++dz)
+                    for (int dy = -r; dy <= r; ++dy)
+                        for (int dx = -r; dx <= r; ++dx)
+                            s += c[((dz + r) * w + (dy + r)) * w + (dx + r)] *
+                                 in[at(g, z + dz, y + dy, x + dx)];
+                out[at(g, z, y, x)] = s;
+            }
+}
+
+/* Transpose of the star operator on the interior (zero outside it):
+ * out(q) = sum_{a,k} c[a][k+r] * in(q - k e_a), with in read as 0 off the interior. */
+static void star_transpose(const double *in, double *out, const orc_grid *g, int r,
+                           const double *c) {
+    const int w = 2 * r + 1;
+    const double *cs[3] = {c, c + w, c + 2 * w};
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) {
+                double s = 0.0;
+                for (int a = 0; a < 3; ++a)
+                    for (int k = -r; k <= r; ++k) {
+                        long zz = z - (a == 0 ? k : 0);
+                        long yy = y - (a == 1 ? k : 0);
+                        long xx = x - (a == 2 ? k : 0);
+                        if (zz < 0 || zz >= g->nz || yy < 0 || yy >= g->ny || xx < 0 || xx >= g->nx)
+                            continue;
+                        s += cs[a][k + r] * in[at(g, zz, yy, xx)];
+                    }
+                out[at(g, z, y, x)] = s;
+            }
+}
+
+/* One-dimensional damping profile of the absorbing sponge.  Cell i of n is at
+ * distance d from the nearest damped face (d = i from the low face, n-1-i from
+ * the high face); inside the layer (d < W) the factor is exp(-(alpha (W - d))^2),
+ * elsewhere 1. */
+void orc_sponge_1d(long n, int W, double alpha, int damp_lo, int damp_hi, double *g) {
+    for (long i = 0; i < n; ++i) {
+        double f = 1.0;
+        if (damp_lo && i < W) f *= exp(-pow(alpha * (double)(W - i), 2.0));
+        long j = n - 1 - i;
+        if (damp_hi && j < W) f *= exp(-pow(alpha * (double)(W - j), 2.0));
+        g[i] = f;
+    }
+}
+
+typedef struct {
+    orc_grid g;
+    int r;
+    const double *lap;    /* r+1 per-axis weights at unit spacing: centre, k = 1..r */
+    const double *c2;     /* padded: (v dt / h)^2 */
+    int sponge_width;
+    double sponge_alpha;
+    int sponge_faces;     /* 1 x-lo, 2 x-hi, 4 y-lo, 8 y-hi, 16 z-lo, 32 z-hi */
+    long src_z, src_y, src_x;
+    const double *src;    /* [nt]: dt^2 f(n dt) */
+    int nt;
+} orc_wave;
+
+/* Full-grid damping factor G(z,y,x) = gz(z) gy(y) gx(x), interior only. */
+static double *sponge_field(const orc_wave *w) {
+    const orc_grid *g = &w->g;
+    double *gx = malloc(sizeof(double) * g->nx);
+    double *gy = malloc(sizeof(double) * g->ny);
+    double *gz = malloc(sizeof(double) * g->nz);
+    orc_sponge_1d(g->nx, w->sponge_width, w->sponge_alpha, w->sponge_faces & 1, w->sponge_faces & 2, gx);
+    orc_sponge_1d(g->ny, w->sponge_width, w->sponge_alpha, w->sponge_faces & 4, w->sponge_faces & 8, gy);
+    orc_sponge_1d(g->nz, w->sponge_width, w->sponge_alpha, w->sponge_faces & 16, w->sponge_faces & 32, gz);
+    double *G = calloc((size_t)(g->nz + 2 * g->H) * g->sz, sizeof(double));
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) G[at(g, z, y, x)] = gz[z] * gy[y] * gx[x];
+    free(gx); free(gy); free(gz);
+    return G;
+}
+
+static void lap_table(const orc_wave *w, double *c) {
+    const int r = w->r, n = 2 * r + 1;
+    for (int a = 0; a < 3; ++a)
+        for (int k = -r; k <= r; ++k) c[a * n + k + r] = w->lap[k < 0 ? -k : k];
+}
+
+static size_t field_len(const orc_grid *g) { return (size_t)(g->nz + 2 * g->H) * g->sz; }
+
+/* One forward step n (1 <= n < nt), G given:
+ *   u^{n+1} = G (2 u^n - G u^{n-1} + C2 S u^n) + dt^2 f^n delta_src
+ * Also records the receiver plane d^n = u^n(z = 0) into trace (ny*nx) and adds
+ * (u^{n+1})^2 to image when those are non-NULL. */
+static void step_with_G(const orc_wave *w, const double *G, const double *lapc, int n,
+                        const double *uprev, const double *ucur, double *unext,
+                        double *trace, double *image, double *work) {
+    const orc_grid *g = &w->g;
+    orc_star(ucur, work, g, w->r, lapc);
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) {
+                long i = at(g, z, y, x);
+                unext[i] = G[i] * (2.0 * ucur[i] - G[i] * uprev[i] + w->c2[i] * work[i]);
+            }
+    if (n >= 0 && n < w->nt) unext[at(g, w->src_z, w->src_y, w->src_x)] += w->src[n];
+    if (trace)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) trace[y * g->nx + x] = ucur[at(g, 0, y, x)];
+    if (image)
+        for (long z = 0; z < g->nz; ++z)
+            for (long y = 0; y < g->ny; ++y)
+                for (long x = 0; x < g->nx; ++x) {
+                    long i = at(g, z, y, x);
+                    image[i] += unext[i] * unext[i];
+                }
+}
+
+void orc_wave_step(const orc_wave *w, int n, const double *uprev, const double *ucur,
+                   double *unext, double *trace, double *image) {
+    double *G = sponge_field(w);
+    double lapc[27];
+    lap_table(w, lapc);
+    double *work = calloc(field_len(&w->g), sizeof(double));
+    step_with_G(w, G, lapc, n, uprev, ucur, unext, trace, image, work);
+    free(work); free(G);
+}
+
+/* Forward run.  Inputs u^0, u^1; steps n = 1..nt-1 produce u^2..u^nt.
+ * traces: [nt][ny][nx], d^n = u^n(z = 0) for n = 0..nt-1.
+ * states: NULL, or (nt+1) padded fields receiving u^0..u^nt.
+ * last:   NULL, or 2 padded fields receiving u^{nt-1}, u^nt.
+ * image:  NULL, or a padded field that accumulates sum_n (u^{n+1})^2. */
+void orc_wave_forward(const orc_wave *w, const double *u0, const double *u1, double *traces,
+                      double *states, double *last, double *image) {
+    const orc_grid *g = &w->g;
+    const size_t L = field_len(g);
+    double *G = sponge_field(w);
+    double lapc[27];
+    lap_table(w, lapc);
+    double *a = malloc(L * sizeof(double)), *b = malloc(L * sizeof(double));
+    double *c = calloc(L, sizeof(double)), *work = calloc(L, sizeof(double));
+    memcpy(a, u0, L * sizeof(double));
+    memcpy(b, u1, L * sizeof(double));
+    for (long y = 0; y < g->ny; ++y)
+        for (long x = 0; x < g->nx; ++x) traces[y * g->nx + x] = a[at(g, 0, y, x)];
+    if (states) {
+        memcpy(states, a, L * sizeof(double));
+        memcpy(states + L, b, L * sizeof(double));
+    }
+    for (int n = 1; n < w->nt; ++n) {
+        double *tr = traces + (size_t)n * g->ny * g->nx;
+        step_with_G(w, G, lapc, n, a, b, c, tr, image, work);
+        double *t = a; a = b; b = c; c = t;  /* a = u^n, b = u^{n+1} */
+        if (states) memcpy(states + (size_t)(n + 1) * L, b, L * sizeof(double));
+    }
+    if (last) {
+        memcpy(last, a, L * sizeof(double));
+        memcpy(last + L, b, L * sizeof(double));
+    }
+    free(a); free(b); free(c); free(work); free(G);
+}
+
+/* One adjoint step n, G given.  For n >= 1:
+ *   lam^n = 2 G lam^{n+1} - G^2 lam^{n+2} + S^T (C2 G lam^{n+1}) + R^T r^n
+ *   grad_c2 += G lam^{n+1} S u^n
+ * For n = 0 (u^0 enters only through the G^2 term of step 1 and the receivers):
+ *   lam^0 = -G^2 lam^2 + R^T r^0. */
+static void adjoint_with_G(const orc_wave *w, const double *G, const double *lapc, int n,
+                           const double *lam2, const double *lam1, double *lam0,
+                           const double *resid, const double *un, double *grad,
+                           double *work, double *work2) {
+    const orc_grid *g = &w->g;
+    if (n >= 1) {
+#pragma omp parallel for schedule(static)
+        for (long z = 0; z < g->nz; ++z)
+            for (long y = 0; y < g->ny; ++y)
+                for (long x = 0; x < g->nx; ++x) {
+                    long i = at(g, z, y, x);
+                    work[i] = w->c2[i] * G[i] * lam1[i];
+                }
+        star_transpose(work, work2, g, w->r, lapc);
+        if (grad) orc_star(un, work, g, w->r, lapc);
+    }
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) {
+                long i = at(g, z, y, x);
+                double v = -G[i] * G[i] * lam2[i];
+                if (n >= 1) {
+                    v += 2.0 * G[i] * lam1[i] + work2[i];
+                    if (grad) grad[i] += G[i] * lam1[i] * work[i];
+                }
+                lam0[i] = v;
+            }
+    if (resid)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) lam0[at(g, 0, y, x)] += resid[y * g->nx + x];
+}
+
+void orc_adjoint_step(const orc_wave *w, int n, const double *lam2, const double *lam1,
+                      double *lam0, const double *resid, const double *un, double *grad) {
+    const size_t L = field_len(&w->g);
+    double *G = sponge_field(w);
+    double lapc[27];
+    lap_table(w, lapc);
+    double *work = calloc(L, sizeof(double)), *work2 = calloc(L, sizeof(double));
+    adjoint_with_G(w, G, lapc, n, lam2, lam1, lam0, resid, un, grad, work, work2);
+    free(work); free(work2); free(G);
+}
+
+/* Full adjoint run over stored forward states u^0..u^nt (only u^1..u^{nt-1} are
+ * read).  resid: [nt][ny][nx] = d - d_obs.  Outputs: grad_c2 (padded, overwritten),
+ * lam0 = dJ/du^0, lam1 = dJ/du^1, and, if grad_src is non-NULL, dJ/d(dt^2 f^n)
+ * = lam^{n+1}(src) for n = 1..nt-1 (lam^nt = 0; f^0 is unused, its entry is 0). */
+void orc_wave_adjoint(const orc_wave *w, const double *states, const double *resid,
+                      double *grad_c2, double *lam0_out, double *lam1_out, double *grad_src) {
+    const orc_grid *g = &w->g;
+    const size_t L = field_len(g);
+    const size_t P = (size_t)g->ny * g->nx;
+    double *G = sponge_field(w);
+    double lapc[27];
+    lap_table(w, lapc);
+    double *l2 = calloc(L, sizeof(double)), *l1 = calloc(L, sizeof(double));
+    double *l0 = calloc(L, sizeof(double));
+    double *work = calloc(L, sizeof(double)), *work2 = calloc(L, sizeof(double));
+    memset(grad_c2, 0, L * sizeof(double));
+    const long isrc = at(g, w->src_z, w->src_y, w->src_x);
+    if (grad_src) {
+        grad_src[0] = 0.0;          /* f^0 is never injected: u^1 is an input */
+        grad_src[w->nt - 1] = 0.0;  /* lam^nt = 0 */
+    }
+    for (int n = w->nt - 1; n >= 0; --n) {
+        adjoint_with_G(w, G, lapc, n, l2, l1, l0, resid + (size_t)n * P,
+                       n >= 1 ? states + (size_t)n * L : NULL, grad_c2, work, work2);
+        if (grad_src && n >= 2) grad_src[n - 1] = l0[isrc];
+        double *t = l2; l2 = l1; l1 = l0; l0 = t;  /* l1 = lam^n, l2 = lam^{n+1} */
+        if (n == 1) memcpy(lam1_out, l1, L * sizeof(double));
+    }
+    memcpy(lam0_out, l1, L * sizeof(double));
+    free(l2); free(l1); free(l0); free(work); free(work2); free(G);
+}

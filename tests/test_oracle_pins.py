@@ -1,0 +1,458 @@
+"""Pins of the FP64 oracle to facts fixed outside of it.
+
+Each test ties an oracle routine to something other than the oracle itself: the
+point counts that Table I prints, the closed-form central-difference weights and
+their moment conditions, exact derivatives of polynomials, the measured order of
+accuracy, library correlations (scipy.ndimage) that compute the same definition,
+the discrete energy that leapfrog conserves, reciprocity of the Green's function,
+the dot-product identity of forward and adjoint and finite differences of the
+misfit.  All of them run on the CPU.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- coefficients
+def fornberg_second_derivative(r):
+    """Closed form of the symmetric 2r-th order weights of d2/dx2 at unit spacing."""
+    c0 = -2 * sum(Fraction(1, k * k) for k in range(1, r + 1))
+    ck = [Fraction(2 * (-1) ** (k + 1) * math.factorial(r) ** 2,
+                   k * k * math.factorial(r - k) * math.factorial(r + k)) for k in range(1, r + 1)]
+    return [c0] + ck
+
+
+def moment_solve(r):
+    """Solve sum_k c_k k^(2j) = 2 [j == 1], j = 0..r, for symmetric weights (exact)."""
+    n = r + 1
+    A = [[Fraction(1 if k == 0 else 0) if j == 0 else Fraction(0) for k in range(n)] for j in range(n)]
+    for j in range(n):
+        for k in range(n):
+            A[j][k] = Fraction(1) if (j == 0 and k == 0) else (
+                Fraction(0) if k == 0 else Fraction(2 * k ** (2 * j)))
+    b = [Fraction(2 if j == 1 else 0) for j in range(n)]
+    for col in range(n):  # Gauss-Jordan in rationals
+        piv = next(i for i in range(col, n) if A[i][col] != 0)
+        A[col], A[piv] = A[piv], A[col]
+        b[col], b[piv] = b[piv], b[col]
+        for i in range(n):
+            if i != col and A[i][col] != 0:
+                f = A[i][col] / A[col][col]
+                A[i] = [a - f * c for a, c in zip(A[i], A[col])]
+                b[i] -= f * b[col]
+    return [b[i] / A[i][i] for i in range(n)]
+
+
+def test_laplacian_weights_closed_form():
+    assert fornberg_second_derivative(4) == list(synth.LAPLACIAN_R4)
+    assert moment_solve(4) == list(synth.LAPLACIAN_R4)
+    for r in (1, 2, 3):
+        assert fornberg_second_derivative(r) == moment_solve(r)
+    assert fornberg_second_derivative(1) == [Fraction(-2), Fraction(1)]
+
+
+def exact_weights(r):
+    half = [float(f) for f in fornberg_second_derivative(r)]
+    w = np.array(half[:0:-1] + half)
+    return np.stack([w, w, w])
+
+
+# ---------------------------------------------------------- shapes (Table I)
+def read_table1():
+    rows = []
+    with open(os.path.join(GOLDEN, "table1_points.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, dims, shape, r, pts = line.split()
+            rows.append((name, int(dims), shape, int(r), int(pts)))
+    return rows
+
+
+@pytest.mark.parametrize("row", [r for r in read_table1() if r[1] == 3], ids=lambda r: r[0])
+def test_point_counts_match_table1(row):
+    """The impulse response of the oracle touches exactly the Table I point count."""
+    _, _, shape, r, pts = row
+    n = 2 * r + 3
+    rng = np.random.default_rng(5)
+    acc = np.zeros((n, n, n))
+    for trial in range(2):  # random non-zero coefficients: no accidental cancellation
+        if shape == "star":
+            c = rng.uniform(0.5, 1.5, (3, 2 * r + 1))
+        else:
+            c = rng.uniform(0.5, 1.5, (2 * r + 1,) * 3)
+        delta = synth.padded_zeros(n, n, n, dtype=np.float64)
+        synth.interior(delta, n, n, n)[n // 2, n // 2, n // 2] = 1.0
+        f = oracle.star if shape == "star" else oracle.box
+        out = f(delta, n, n, n, r, c)
+        acc += np.abs(synth.interior(out, n, n, n))
+    assert int(np.count_nonzero(acc)) == pts
+
+
+# ------------------------------------------------------------- star oracle
+def poly_field(deg_max, seed, n=12, halo=4, pure_x_degree=None):
+    """Random polynomial of total degree <= deg_max on the padded grid incl. halo,
+    with its exact Laplacian (grid units).  Coordinates scaled to ~[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    N = n + 2 * halo
+    s = n / 2.0
+    idx = (np.arange(N) - halo - (n - 1) / 2.0) / s
+    Z, Y, X = np.meshgrid(idx, idx, idx, indexing="ij")
+    u = np.zeros((N, N, N))
+    lap = np.zeros((N, N, N))
+    terms = []
+    if pure_x_degree is not None:
+        terms = [(pure_x_degree, 0, 0, 1.0)]
+    else:
+        for i in range(deg_max + 1):
+            for j in range(deg_max + 1 - i):
+                for k in range(deg_max + 1 - i - j):
+                    terms.append((i, j, k, rng.uniform(-1, 1)))
+    for i, j, k, a in terms:
+        u += a * X ** i * Y ** j * Z ** k
+        if i >= 2:
+            lap += a * i * (i - 1) * X ** (i - 2) * Y ** j * Z ** k / s ** 2
+        if j >= 2:
+            lap += a * j * (j - 1) * X ** i * Y ** (j - 2) * Z ** k / s ** 2
+        if k >= 2:
+            lap += a * k * (k - 1) * X ** i * Y ** j * Z ** (k - 2) / s ** 2
+    return u, lap
+
+
+def test_star_exact_on_degree_9_polynomials():
+    n = 12
+    u, lap = poly_field(9, seed=1, n=n)
+    out = oracle.star(u, n, n, n, 4, exact_weights(4))
+    got = synth.interior(out, n, n, n)
+    want = synth.interior(lap, n, n, n)
+    assert np.max(np.abs(got - want)) <= 1e-10 * max(1.0, np.max(np.abs(want)))
+
+
+def test_star_not_exact_at_degree_10():
+    n = 12
+    u, lap = poly_field(10, seed=0, n=n, pure_x_degree=10)
+    out = oracle.star(u, n, n, n, 4, exact_weights(4))
+    err = np.max(np.abs(synth.interior(out, n, n, n) - synth.interior(lap, n, n, n)))
+    # the first neglected moment: sum_k c_k k^10 / 10! * d^10/dx^10 (X^10) / s^10
+    s = n / 2.0
+    expect = 2 * 576 / math.factorial(10) * math.factorial(10) / s ** 10
+    assert abs(err - expect) < 1e-6 * expect
+
+
+def test_star_constant_field_is_zero():
+    n = 10
+    u = np.full((n + 8, n + 8, n + 8), 3.25)
+    out = oracle.star(u, n, n, n, 4, exact_weights(4))
+    assert np.max(np.abs(synth.interior(out, n, n, n))) < 1e-13
+    # zero halo: interior points at least r away from every face still see a constant
+    z = synth.padded_zeros(n, n, n, dtype=np.float64)
+    synth.interior(z, n, n, n)[...] = 3.25
+    out = oracle.star(z, n, n, n, 4, exact_weights(4))
+    assert np.max(np.abs(synth.interior(out, n, n, n)[4:-4, 4:-4, 4:-4])) < 1e-13
+
+
+def sine_error(ppw, n=16):
+    """Max relative error of the star on sin(kx)sin(ky)sin(kz) vs -|k|^2 u."""
+    k = 2 * np.pi / ppw
+    N = n + 8
+    idx = np.arange(N) - 4.0
+    Z, Y, X = np.meshgrid(idx, idx, idx, indexing="ij")
+    u = np.sin(k * X + 0.3) * np.sin(k * Y + 0.7) * np.sin(k * Z + 1.1)
+    out = oracle.star(u, n, n, n, 4, exact_weights(4))
+    got = synth.interior(out, n, n, n)
+    want = -3 * k * k * synth.interior(u, n, n, n)
+    return np.max(np.abs(got - want)) / np.max(np.abs(want))
+
+
+def test_star_convergence_order_8():
+    ppws = np.array([16.0, 24.0, 32.0, 48.0])
+    errs = np.array([sine_error(p) for p in ppws])
+    slope = np.polyfit(np.log(ppws), np.log(errs), 1)[0]
+    assert abs(slope + 8.0) < 0.3
+
+
+def test_star_truncation_constant():
+    """1-D symbol: c0 + 2 sum c_k cos(k t) = -t^2 + t^10/3150 + O(t^12).
+
+    R(t) = (symbol + t^2) / t^10 is measured on a sine along x and extrapolated
+    to t -> 0 by a quadratic fit in t^2 (the O(t^12), O(t^14) terms)."""
+    n = 8
+    ts, rs = [], []
+    for ppw in (10.0, 12.0, 16.0, 20.0):
+        t = 2 * np.pi / ppw
+        N = n + 8
+        idx = np.arange(N) - 4.0
+        u = np.broadcast_to(np.sin(t * idx + 0.4)[None, None, :], (N, N, N)).copy()
+        out = oracle.star(u, n, n, n, 4, exact_weights(4))
+        got = synth.interior(out, n, n, n)
+        ui = synth.interior(u, n, n, n)
+        mask = np.abs(ui) > 0.5
+        ts.append(t * t)
+        rs.append(np.mean((got + t * t * ui)[mask] / ui[mask]) / t ** 10)
+    fit = np.polyfit(ts, rs, 2)
+    assert abs(fit[-1] * 3150 - 1) < 1e-4
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_star_matches_scipy_correlate1d(r):
+    nx, ny, nz = 11, 9, 7
+    rng = np.random.default_rng(10 + r)
+    a = synth.padded_zeros(nx, ny, nz, dtype=np.float64)
+    a[...] = rng.uniform(-1, 1, a.shape)  # non-zero halo is read as stored
+    c = rng.uniform(-1, 1, (3, 2 * r + 1))
+    out = oracle.star(a, nx, ny, nz, r, c)
+    full = a[:, :, :nx + 8]
+    ref = (ndimage.correlate1d(full, c[0], axis=0, mode="constant")
+           + ndimage.correlate1d(full, c[1], axis=1, mode="constant")
+           + ndimage.correlate1d(full, c[2], axis=2, mode="constant"))
+    np.testing.assert_allclose(synth.interior(out, nx, ny, nz),
+                               ref[4:4 + nz, 4:4 + ny, 4:4 + nx], rtol=0, atol=1e-13)
+
+
+# -------------------------------------------------------------- box oracle
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_box_matches_scipy_correlate(r):
+    nx, ny, nz = 10, 7, 6
+    rng = np.random.default_rng(20 + r)
+    a = synth.padded_zeros(nx, ny, nz, dtype=np.float64)
+    a[...] = rng.uniform(-1, 1, a.shape)
+    c = rng.uniform(-1, 1, (2 * r + 1,) * 3)  # no symmetry: a transposed axis fails
+    out = oracle.box(a, nx, ny, nz, r, c)
+    ref = ndimage.correlate(a[:, :, :nx + 8], c, mode="constant")
+    np.testing.assert_allclose(synth.interior(out, nx, ny, nz),
+                               ref[4:4 + nz, 4:4 + ny, 4:4 + nx], rtol=0, atol=1e-12)
+
+
+def test_box_dense_operator_8cubed():
+    """Brute force: the dense 512x512 zero-halo operator built from numpy shifts."""
+    n, r = 8, 2
+    rng = np.random.default_rng(3)
+    c = rng.uniform(-1, 1, (5, 5, 5))
+    M = np.zeros((n ** 3, n ** 3))
+    for q in range(n ** 3):  # column q = response to a unit impulse at q
+        e = np.zeros((n, n, n))
+        e.flat[q] = 1.0
+        pad = np.pad(e, r)
+        col = np.zeros((n, n, n))
+        for dz in range(-r, r + 1):
+            for dy in range(-r, r + 1):
+                for dx in range(-r, r + 1):
+                    col += c[dz + r, dy + r, dx + r] * pad[r + dz:r + dz + n, r + dy:r + dy + n,
+                                                          r + dx:r + dx + n]
+        M[:, q] = col.ravel()
+    x = rng.uniform(-1, 1, (n, n, n))
+    a = synth.padded_zeros(n, n, n, dtype=np.float64)
+    synth.interior(a, n, n, n)[...] = x
+    out = oracle.box(a, n, n, n, r, c)
+    np.testing.assert_allclose(synth.interior(out, n, n, n).ravel(), M @ x.ravel(),
+                               rtol=0, atol=1e-13)
+
+
+def test_box_separable_and_r1_star():
+    n = 9
+    rng = np.random.default_rng(4)
+    a = synth.padded_zeros(n, n, n, dtype=np.float64)
+    synth.interior(a, n, n, n)[...] = rng.uniform(-1, 1, (n, n, n))
+    az, ay, ax = (rng.uniform(-1, 1, 9) for _ in range(3))
+    c = az[:, None, None] * ay[None, :, None] * ax[None, None, :]
+    out = oracle.box(a, n, n, n, 4, c)
+    x = a[:, :, :n + 8]
+    ref = ndimage.correlate1d(ndimage.correlate1d(ndimage.correlate1d(
+        x, az, axis=0, mode="constant"), ay, axis=1, mode="constant"), ax, axis=2, mode="constant")
+    np.testing.assert_allclose(synth.interior(out, n, n, n), ref[4:-4, 4:-4, 4:-4], atol=1e-13)
+    # r = 1 box holding the 7-point Laplacian pattern equals the r = 1 star
+    c7 = np.zeros((3, 3, 3))
+    c7[1, 1, 1] = -6
+    for d in ((0, 1, 1), (2, 1, 1), (1, 0, 1), (1, 2, 1), (1, 1, 0), (1, 1, 2)):
+        c7[d] = 1
+    s = np.array([[1, -2, 1]] * 3, dtype=np.float64)
+    np.testing.assert_allclose(oracle.box(a, n, n, n, 1, c7), oracle.star(a, n, n, n, 1, s),
+                               atol=1e-14)
+
+
+# ------------------------------------------------------------------ sponge
+def test_sponge_profile_closed_form():
+    g = oracle.sponge_1d(100, 32, 0.015, True, True)
+    assert g[0] == pytest.approx(math.exp(-(0.015 * 32) ** 2), rel=1e-15)
+    assert g[99] == pytest.approx(math.exp(-(0.015 * 32) ** 2), rel=1e-15)
+    assert g[31] == pytest.approx(math.exp(-0.015 ** 2), rel=1e-15)
+    assert np.all(g[32:68] == 1.0)
+    assert np.all(np.diff(g[:33]) > 0)
+    g1 = oracle.sponge_1d(100, 32, 0.015, False, True)
+    assert np.all(g1[:68] == 1.0) and g1[99] == g[99]
+
+
+# -------------------------------------------------------------- wave oracle
+def wave_problem(n, c2_value, seed, nt, lap=None, src=None, f=None, faces=0, width=0,
+                 alpha=0.0, rand_c2=True):
+    rng = np.random.default_rng(seed)
+    c2 = synth.padded_zeros(n, n, n, dtype=np.float64)
+    if rand_c2:
+        synth.interior(c2, n, n, n)[...] = c2_value * rng.uniform(0.5, 1.0, (n, n, n))
+    else:
+        synth.interior(c2, n, n, n)[...] = c2_value
+    lap = [float(v) for v in synth.LAPLACIAN_R4] if lap is None else lap
+    src = (n // 2, n // 2, n // 2) if src is None else src
+    f = np.zeros(nt) if f is None else f
+    return oracle.Wave(n, n, n, c2, lap, src, f, nt, width, alpha, faces)
+
+
+def energy(w, up, u, n):
+    """E^{n+1/2} = sum (u^{n+1}-u^n)^2 / C2 - <u^{n+1}, S u^n>, interior sums."""
+    lapc = np.array([w.lap[abs(k)] for k in range(-4, 5)])
+    Su = oracle.star(up, n, n, n, 4, np.stack([lapc] * 3))
+    I = lambda a: synth.interior(a, n, n, n)
+    return np.sum((I(u) - I(up)) ** 2 / I(w.c2)) - np.sum(I(u) * I(Su))
+
+
+def test_leapfrog_conserves_discrete_energy():
+    n, nt = 16, 300
+    w = wave_problem(n, 0.16, seed=1, nt=nt)
+    u0 = synth.smooth_random_grid(2, n, n, n).astype(np.float64)
+    u1 = synth.smooth_random_grid(3, n, n, n).astype(np.float64)
+    e0 = energy(w, u0, u1, n)
+    res = w.forward(u0, u1)
+    a, b = res["last"]
+    e1 = energy(w, a, b, n)
+    assert e0 > 0
+    assert abs(e1 - e0) <= 1e-12 * e0
+
+
+def test_cfl_limit():
+    """Stable just below the 8th-order 3-D limit 2/sqrt(3*6.5016) = 0.4529, unstable above."""
+    n, nt = 12, 1500
+    checker = synth.padded_zeros(n, n, n, dtype=np.float64)
+    idx = np.indices((n, n, n)).sum(axis=0)
+    synth.interior(checker, n, n, n)[...] = (-1.0) ** idx
+    out = {}
+    for courant in (0.44, 0.47):
+        w = wave_problem(n, courant ** 2, seed=0, nt=nt, rand_c2=False)
+        res = w.forward(checker, checker * 0.999)
+        out[courant] = np.max(np.abs(res["last"][1]))
+    assert out[0.44] < 10.0
+    assert out[0.47] > 1e3
+
+
+def test_reciprocity():
+    n, nt = 14, 120
+    rng = np.random.default_rng(7)
+    f = rng.standard_normal(nt)
+    s1, s2 = (4, 5, 6), (9, 8, 7)
+    w1 = wave_problem(n, 0.12, seed=9, nt=nt, src=s1, f=f)
+    w2 = wave_problem(n, 0.12, seed=9, nt=nt, src=s2, f=f)
+    z = np.zeros(w1.shape)
+    st1 = w1.forward(z, z, keep_states=True)["states"]
+    st2 = w2.forward(z, z, keep_states=True)["states"]
+    at = lambda p: (p[0] + 4, p[1] + 4, p[2] + 4)
+    # C2(s) u_s(r) = C2(r) u_r(s): D u'' = S u + f delta_s / C2(s) with symmetric D, S
+    lhs = w1.c2[at(s2)] * st2[:, at(s1)[0], at(s1)[1], at(s1)[2]]
+    rhs = w1.c2[at(s1)] * st1[:, at(s2)[0], at(s2)[1], at(s2)[2]]
+    assert np.max(np.abs(lhs - rhs)) <= 1e-12 * np.max(np.abs(lhs))
+    assert np.max(np.abs(lhs)) > 0
+
+
+def sponge_problem(n, nt, seed, f=None):
+    return wave_problem(n, 0.15, seed=seed, nt=nt, src=(2, n // 2, n // 2), f=f,
+                        faces=synth.SPONGE_LATERAL_AND_BOTTOM, width=4, alpha=0.1)
+
+
+def test_adjoint_dot_product_fp64():
+    n, nt = 12, 60
+    rng = np.random.default_rng(11)
+    f = rng.standard_normal(nt)
+    w = sponge_problem(n, nt, seed=12, f=f)
+    u0 = synth.smooth_random_grid(13, n, n, n, sigma=1.5).astype(np.float64)
+    u1 = synth.smooth_random_grid(14, n, n, n, sigma=1.5).astype(np.float64)
+    res = w.forward(u0, u1, keep_states=True)
+    y = rng.standard_normal((nt, n, n))
+    _, l0, l1, gs = w.adjoint(res["states"], y)
+    lhs = np.sum(res["traces"] * y)
+    I = lambda a: synth.interior(a, n, n, n)
+    rhs = np.sum(I(u0) * I(l0)) + np.sum(I(u1) * I(l1)) + np.sum(f * gs)
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_adjoint_single_step_matches_full_run():
+    """The step routine reproduces the full adjoint run's recursion."""
+    n, nt = 10, 12
+    rng = np.random.default_rng(15)
+    w = sponge_problem(n, nt, seed=16)
+    u0 = synth.smooth_random_grid(17, n, n, n).astype(np.float64)
+    u1 = synth.smooth_random_grid(18, n, n, n).astype(np.float64)
+    st = w.forward(u0, u1, keep_states=True)["states"]
+    y = rng.standard_normal((nt, n, n))
+    g_full, l0_full, l1_full, _ = w.adjoint(st, y)
+    l2, l1 = w.zeros(), w.zeros()
+    g = w.zeros()
+    for k in range(nt - 1, -1, -1):
+        l0 = w.adjoint_step(k, l2, l1, y[k], st[k] if k >= 1 else None, g)
+        l2, l1 = l1, l0
+        if k == 1:
+            lam1 = l0.copy()
+    np.testing.assert_allclose(l1, l0_full, rtol=0, atol=1e-12 * np.abs(l0_full).max())
+    np.testing.assert_allclose(lam1, l1_full, rtol=0, atol=1e-12 * np.abs(l1_full).max())
+    np.testing.assert_allclose(g, g_full, rtol=0, atol=1e-12 * np.abs(g_full).max())
+
+
+def test_gradient_finite_differences_fp64():
+    n, nt = 12, 80
+    rng = np.random.default_rng(21)
+    f = np.sin(np.arange(nt) * 0.3) * np.exp(-((np.arange(nt) - 15) / 6.0) ** 2)
+    w = sponge_problem(n, nt, seed=22, f=f)
+    z = np.zeros(w.shape)
+    d_obs = rng.standard_normal((nt, n, n)) * 1e-3
+    res = w.forward(z, z, keep_states=True)
+    resid = res["traces"] - d_obs
+    g, _, _, _ = w.adjoint(res["states"], resid)
+
+    def J(c2):
+        ww = oracle.Wave(n, n, n, c2, w.lap, (2, n // 2, n // 2), f, nt, 4, 0.1,
+                         synth.SPONGE_LATERAL_AND_BOTTOM)
+        d = ww.forward(z, z)["traces"]
+        return 0.5 * np.sum((d - d_obs) ** 2)
+
+    pts = [tuple(rng.integers(0, n, 3)) for _ in range(16)]
+    for p in pts:
+        i = (p[0] + 4, p[1] + 4, p[2] + 4)
+        eps = 1e-4 * w.c2[i]
+        cp, cm = w.c2.copy(), w.c2.copy()
+        cp[i] += eps
+        cm[i] -= eps
+        fd = (J(cp) - J(cm)) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(abs(g[i]), 1e-6 * np.abs(g).max())
+
+
+def test_forward_step_matches_run_and_records_traces():
+    n, nt = 10, 6
+    rng = np.random.default_rng(30)
+    f = rng.standard_normal(nt)
+    w = sponge_problem(n, nt, seed=31, f=f)
+    u0 = synth.smooth_random_grid(32, n, n, n).astype(np.float64)
+    u1 = synth.smooth_random_grid(33, n, n, n).astype(np.float64)
+    res = w.forward(u0, u1, keep_states=True, image=True)
+    a, b = u0, u1
+    img = w.zeros()
+    for k in range(1, nt):
+        c, tr = w.step(k, a, b, image=img)
+        np.testing.assert_array_equal(tr, res["traces"][k])
+        np.testing.assert_array_equal(c, res["states"][k + 1])
+        a, b = b, c
+    np.testing.assert_array_equal(res["traces"][0], synth.interior(u0, n, n, n)[0])
+    np.testing.assert_allclose(img, res["image"], rtol=1e-15)
+    # the source enters with weight 1 at its cell when G = 1 there
+    w0 = sponge_problem(n, nt, seed=31, f=np.zeros(nt))
+    c0, _ = w0.step(3, u0, u1)
+    c1, _ = w.step(3, u0, u1)
+    d = c1 - c0
+    assert d[2 + 4, n // 2 + 4, n // 2 + 4] == pytest.approx(f[3], rel=1e-12)
+    d[2 + 4, n // 2 + 4, n // 2 + 4] = 0
+    assert np.max(np.abs(d)) == 0
