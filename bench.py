@@ -1,0 +1,419 @@
+#!/usr/bin/env python3
+"""Benchmark of the MMStencil hot path on one MI355X.
+
+Headline workload (the value of the JSON line): FP32 sweeps of a 512^3 grid
+with a 4-cell zero halo and uniform [-1, 1] data (seed 2) through three
+stencils -- the radius-4 25-point star (8th-order Laplacian), a radius-2
+125-point box and a radius-4 729-point box (uniform [-1, 1] weights with the
+mean removed, seeds 3 and 4).  One step = one sweep of each stencil; the value
+is interior points swept per second over the timed steps (Gpoints/s).
+
+Besides the headline the same JSON line carries, each measured in this run:
+  * "kernels": per-stencil Gpoints/s, achieved GB/s or TFLOP/s and the max /
+    RMS error against the FP64 oracle at 4000 sampled points;
+  * "split_mfma": the radius-4 and radius-3 boxes three ways (FP32 VALU, BF16x3
+    and FP16x3S split MFMA, plus the BF16x1 error report);
+  * "rtm": the 400^3, 2000-step acoustic forward model with FP64 imaging;
+  * "gradient": the 256^3, 1000-step adjoint gradient with checkpointing,
+    with its dot-product test;
+  * "roofline" of the dominant kernel and "cpu_baseline" (the FP64 oracle on
+    the host cores over a bounded sample of the headline workload).
+
+Kernels run on torch's current stream; HIP events recorded on that stream
+bracket every launch, so per-kernel times come from the same events.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gpoints/s per sweep (FP32 vs split-MFMA at <=1e-5 rel err); % HBM/MFMA peak"
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TF = 157.3   # published vector FP32 (packed) peak
+MFMA_BF16_PEAK_TF = 2516.6  # published dense BF16/FP16 MFMA peak
+LAP = None
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=100)
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--n", type=int, default=512, help="headline grid edge")
+    p.add_argument("--only", default="", help="profile one kernel: star|box2|box4|box4_bf16x3|"
+                   "box4_fp16x3s|box3_bf16x3|wave|copy")
+    p.add_argument("--skip", default="", help="comma list of extras to skip: "
+                   "split,rtm,gradient,cpu,check")
+    p.add_argument("--cpu-planes", type=int, default=0, help="oracle sample depth (0 = auto)")
+    return p.parse_args()
+
+
+class Timer:
+    """Per-kernel HIP event pairs on torch's current stream."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.pairs = {}
+
+    def run(self, name, fn):
+        t = self.torch
+        a, b = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        self.pairs.setdefault(name, []).append((a, b))
+
+    def ms(self, name):
+        return float(np.mean([a.elapsed_time(b) for a, b in self.pairs[name]]))
+
+    def reset(self):
+        self.pairs = {}
+
+
+def sample_points(n, count, seed):
+    rng = np.random.default_rng(seed)
+    pts = rng.integers(0, n, (count, 3))
+    edge = np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, n // 2], [n - 1, 0, 0]])
+    return np.concatenate([pts, edge])
+
+
+def errors(got, ref):
+    d = got.astype(np.float64) - ref
+    return (float(np.max(np.abs(d)) / np.max(np.abs(ref))),
+            float(np.linalg.norm(d) / np.linalg.norm(ref)))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported "
+              "(the multi-GPU z-slab decomposition is a design note, not built)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2507_11067_amd as mms
+    import synth
+
+    global LAP
+    LAP = [float(v) for v in synth.LAPLACIAN_R4]
+    skip = set(s for s in args.skip.split(",") if s)
+    dev = torch.device("cuda:0")
+    n = args.n
+    grid = mms.Grid(n, n, n)
+    log(f"[bench] generating {n}^3 input (seed 2)")
+    x_np = synth.uniform_grid(2, n, n, n, sy=grid.sy)
+    x = torch.from_numpy(x_np).to(dev)
+    outs = {k: grid.zeros(dev) for k in ("star", "box2", "box4")}
+    c_star = synth.star_coeffs_laplacian(4)
+    c_box2 = synth.box_coeffs(3, 2)
+    c_box4 = synth.box_coeffs(4, 4)
+    c_box3 = synth.box_coeffs(6, 3)
+    sweeps = {
+        "star": lambda: mms.stencil_apply(x, outs["star"], grid, "star", 4, c_star),
+        "box2": lambda: mms.stencil_apply(x, outs["box2"], grid, "box", 2, c_box2),
+        "box4": lambda: mms.stencil_apply(x, outs["box4"], grid, "box", 4, c_box4),
+    }
+
+    if args.only:
+        return profile_only(args, torch, mms, synth, grid, x, outs, sweeps, c_box4, c_box3, dev)
+
+    timer = Timer(torch)
+    log(f"[bench] warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        for f in sweeps.values():
+            f()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        for name, f in sweeps.items():
+            timer.run(name, f)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = e0.elapsed_time(e1)
+    ms_step = total_ms / args.steps
+    pts = grid.points
+    value = 3 * pts / (ms_step * 1e-3) / 1e9
+    log(f"[bench] {ms_step:.3f} ms/step, {value:.1f} Gpoints/s (wall {wall:.2f} s)")
+
+    kernels = {}
+    per = {"star": ("hbm", 8.0, 50.0), "box2": ("alu", 8.0, 250.0), "box4": ("alu", 8.0, 1458.0)}
+    for name, (bound, bytes_pt, flop_pt) in per.items():
+        ms = timer.ms(name)
+        gpts = pts / (ms * 1e-3) / 1e9
+        kernels[name] = {"ms": ms, "gpoints_s": gpts, "gbs": gpts * bytes_pt,
+                         "tflops": gpts * flop_pt / 1e3,
+                         "hbm_frac": gpts * bytes_pt / HBM_PEAK_GBS,
+                         "valu_frac": gpts * flop_pt / 1e3 / FP32_VALU_PEAK_TF}
+    if "check" not in skip:
+        log("[bench] sampled parity vs FP64 oracle")
+        import oracle
+        x64 = x_np.astype(np.float64)
+        ptsel = sample_points(n, 4000, 14)
+        for name, r, c, fn in (("star", 4, c_star, oracle.star_at), ("box2", 2, c_box2, oracle.box_at),
+                               ("box4", 4, c_box4, oracle.box_at)):
+            ref = fn(x64, n, n, n, r, c, ptsel[:1000] if name == "box4" else ptsel)
+            o = outs[name].cpu().numpy()
+            sel = ptsel[:1000] if name == "box4" else ptsel
+            got = o[sel[:, 0] + 4, sel[:, 1] + 4, sel[:, 2] + 4]
+            kernels[name]["rel_max"], kernels[name]["rel_rms"] = errors(got, ref)
+        del x64
+
+    # dominant kernel of the step: the radius-4 box (FP32 FMA bound)
+    dom = max(kernels, key=lambda k: kernels[k]["ms"])
+    kd = kernels[dom]
+    if per[dom][0] == "hbm":
+        roof = {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": kd["tflops"], "peak": FP32_VALU_PEAK_TF,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = {"star": "star_kernel<4>", "box2": "box_valu_kernel<2>",
+                      "box4": "box_valu_kernel<4>"}[dom]
+    roof["traffic"] = None
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "Gpoints/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{n}^3 FP32 sweeps, one step = radius-4 star + radius-2 box + "
+                               "radius-4 box (4-cell zero halo, uniform [-1,1] seed 2)",
+                   "grid": [n, n, n], "halo": 4, "points_per_step": 3 * pts},
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if "split" not in skip:
+        result["split_mfma"] = bench_split(torch, mms, synth, grid, x, x_np, n, c_box4, c_box3,
+                                           dev, "check" not in skip)
+    del outs
+    if "rtm" not in skip:
+        result["rtm"] = bench_rtm(torch, mms, synth, dev)
+    if "gradient" not in skip:
+        result["gradient"] = bench_gradient(torch, mms, synth, dev)
+    if "cpu" not in skip:
+        result["cpu_baseline"] = cpu_baseline(x_np, n, c_star, c_box2, c_box4, args.cpu_planes)
+    print(json.dumps(result), flush=True)
+
+
+def bench_split(torch, mms, synth, grid, x, x_np, n, c_box4, c_box3, dev, check):
+    """Radius-4 and radius-3 boxes at 512^3 three ways, with errors vs the FP64 oracle."""
+    import oracle
+    out = grid.zeros(dev)
+    res = {}
+    x64 = x_np.astype(np.float64) if check else None
+    sel = sample_points(n, 1000, 15)
+    for r, c in ((4, c_box4), (3, c_box3)):
+        ref = oracle.box_at(x64, n, n, n, r, c, sel) if check else None
+        for prec in ("fp32", "bf16x3", "fp16x3s", "bf16x1"):
+            f = lambda: mms.stencil_apply(x, out, grid, "box", r, c, precision=prec)
+            for _ in range(2):
+                f()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 10
+            a.record()
+            for _ in range(reps):
+                f()
+            b.record()
+            torch.cuda.synchronize()
+            ms = a.elapsed_time(b) / reps
+            gpts = grid.points / (ms * 1e-3) / 1e9
+            e = {"ms": ms, "gpoints_s": gpts}
+            flop = 2 * (2 * r + 1) ** 3
+            if prec == "fp32":
+                e["valu_frac"] = gpts * flop / 1e3 / FP32_VALU_PEAK_TF
+            else:
+                nch = -(-((2 * r + 1) * 24) // 32)
+                mfma_per_tile = (3 if prec != "bf16x1" else 1) * (2 * r + 1) * nch
+                issued = gpts * 1e9 / 256 * mfma_per_tile * 16 * 16 * 32 * 2 / 1e12
+                e["mfma_issued_tflops"] = issued
+                e["mfma_frac"] = issued / MFMA_BF16_PEAK_TF
+                e["algorithmic_tflops"] = gpts * flop / 1e3
+            if check:
+                o = out.cpu().numpy()
+                got = o[sel[:, 0] + 4, sel[:, 1] + 4, sel[:, 2] + 4]
+                e["rel_max"], e["rel_rms"] = errors(got, ref)
+            res[f"box_r{r}_{prec}"] = e
+            log(f"[bench] box r{r} {prec}: {gpts:.1f} Gpoints/s "
+                f"{'rel_max %.2e' % e['rel_max'] if 'rel_max' in e else ''}")
+        res[f"box_r{r}_speedup_bf16x3_over_fp32"] = (res[f"box_r{r}_bf16x3"]["gpoints_s"] /
+                                                     res[f"box_r{r}_fp32"]["gpoints_s"])
+        res[f"box_r{r}_speedup_fp16x3s_over_fp32"] = (res[f"box_r{r}_fp16x3s"]["gpoints_s"] /
+                                                      res[f"box_r{r}_fp32"]["gpoints_s"])
+    return res
+
+
+def bench_rtm(torch, mms, synth, dev, n=400, nt=2000):
+    """Acoustic forward model, 400^3, 2000 steps, FP64 image fused (and without)."""
+    log(f"[bench] rtm setup {n}^3 x {nt}")
+    s = synth.wave_setup(n, nt, seed=7, sponge_width=32)
+    grid = mms.Grid(n, n, n)
+    c2 = torch.from_numpy(s.c2).to(dev)
+    f = torch.from_numpy(s.src_dt2f).to(dev)
+    traces = torch.zeros((nt, n, n), device=dev)
+    image = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+    res = {"grid": [n, n, n], "steps": nt - 1, "dt": s.dt}
+    for with_image in (True, False):
+        w = mms.Wave(grid, c2, LAP, nt, 1.0, s.sponge_width, s.sponge_alpha, s.sponge_faces,
+                     s.src, f, traces, image if with_image else None)
+        bufs = [grid.zeros(dev) for _ in range(3)]
+        image.zero_()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        w.record(0, bufs[0])
+        w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        gpts = grid.points * (nt - 1) / (ms * 1e-3) / 1e9
+        bpp = 32.0 if with_image else 16.0
+        key = "with_image" if with_image else "no_image"
+        res[key] = {"ms_total": ms, "ms_per_step": ms / (nt - 1), "gpoints_s": gpts,
+                    "gbs": gpts * bpp, "hbm_frac": gpts * bpp / HBM_PEAK_GBS}
+        log(f"[bench] rtm {key}: {gpts:.1f} Gpoints/s ({ms:.0f} ms)")
+        if with_image:
+            res["trace_max_abs"] = float(traces.abs().max().item())
+            res["image_sum"] = float(image.sum().item())
+    return res
+
+
+def bench_gradient(torch, mms, synth, dev, n=256, nt=1000, K=50):
+    """Adjoint gradient of the receiver misfit w.r.t. v^2, 256^3, 1000 steps."""
+    from paper_2507_11067_amd.autograd import Problem, misfit, propagate
+    log(f"[bench] gradient setup {n}^3 x {nt}")
+    s = synth.wave_setup(n, nt, seed=8, sponge_width=32)
+    s0 = synth.wave_setup(n, nt, seed=None, sponge_width=32, dt=s.dt)
+    grid = mms.Grid(n, n, n)
+    f = torch.from_numpy(s.src_dt2f).to(dev)
+
+    def mgrid(v):
+        m = synth.padded_zeros(n, n, n)
+        synth.interior(m, n, n, n)[...] = (v ** 2).astype(np.float32)
+        return torch.from_numpy(m).to(dev)
+
+    prob = Problem(grid, tuple(LAP), nt, s.h, s.dt, s.src, f, s.sponge_width, s.sponge_alpha,
+                   s.sponge_faces, checkpoint_every=K)
+    z = grid.zeros(dev)
+    with torch.no_grad():
+        d_obs = propagate(mgrid(s0.v), z, z, prob)
+    m = mgrid(s.v).requires_grad_(True)
+    torch.cuda.synchronize()
+    a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    a.record()
+    traces = propagate(m, z, z, prob)
+    J = misfit(traces, d_obs)
+    b.record()
+    J.backward()
+    c.record()
+    torch.cuda.synchronize()
+    fwd_ms, bwd_ms = a.elapsed_time(b), b.elapsed_time(c)
+    pts = grid.points * (nt - 1)
+    res = {"grid": [n, n, n], "steps": nt - 1, "checkpoint_every": K, "J": float(J.item()),
+           "forward_ms": fwd_ms, "backward_ms": bwd_ms,
+           "gpoints_s": pts / ((fwd_ms + bwd_ms) * 1e-3) / 1e9,
+           "recomputed_steps": prob.stats.get("recomputed_steps")}
+    log(f"[bench] gradient: fwd {fwd_ms:.0f} ms, bwd {bwd_ms:.0f} ms")
+    # dot-product test of the adjoint at the full size: A (u0, u1) -> traces (no source),
+    # tested against y = the misfit residual of the gradient run (a smooth trace field)
+    y = torch.empty_like(traces)
+    mms.flat_misfit(traces.detach(), d_obs, resid=y)
+    w = mms.Wave(grid, m.detach(), LAP, nt, (s.dt / s.h) ** 2, s.sponge_width, s.sponge_alpha,
+                 s.sponge_faces, s.src, None, torch.zeros((nt, n, n), device=dev))
+    u0 = torch.from_numpy(synth.smooth_random_grid(81, n, n, n, sigma=3.0)).to(dev)
+    u1 = torch.from_numpy(synth.smooth_random_grid(82, n, n, n, sigma=3.0)).to(dev)
+    bufs = [u0.clone(), u1.clone(), grid.zeros(dev)]
+    w.record(0, bufs[0])
+    w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+    lam = [grid.zeros(dev) for _ in range(3)]
+    w.adjoint(nt - 1, 0, [lam[i % 3] for i in range(nt + 2)], resid=y)
+    lhs = mms.flat_dot(w.traces, y)
+    rhs = mms.dot(u0, lam[0], grid) + mms.dot(u1, lam[1], grid)
+    res["dot_test"] = {"lhs": lhs, "rhs": rhs, "rel": abs(lhs - rhs) / abs(lhs)}
+    log(f"[bench] dot test rel {res['dot_test']['rel']:.2e}")
+    return res
+
+
+def cpu_baseline(x_np, n, c_star, c_box2, c_box4, planes):
+    """FP64 oracle on the host cores over a slab of the headline input."""
+    import oracle
+    nz = planes if planes > 0 else 32
+    nz = min(nz, n)
+    slab = np.ascontiguousarray(x_np[:nz + 8].astype(np.float64))  # planes -4 .. nz+3
+    cores = len(os.sched_getaffinity(0))
+    threads = int(os.environ.get("OMP_NUM_THREADS", cores))
+    log(f"[bench] cpu baseline: oracle on {n}x{n}x{nz} slab, {threads} threads")
+    t0 = time.perf_counter()
+    oracle.star(slab, n, n, nz, 4, c_star)
+    oracle.box(slab, n, n, nz, 2, c_box2)
+    oracle.box(slab, n, n, nz, 4, c_box4)
+    dt = time.perf_counter() - t0
+    pts = 3 * n * n * nz
+    log(f"[bench] cpu baseline: {dt:.1f} s")
+    return {"value": pts / dt / 1e9, "unit": "Gpoints/s", "cores": min(threads, cores),
+            "kind": "oracle",
+            "sample": f"one sweep each of star r4, box r2, box r4 (FP64) over a {n}x{n}x{nz} "
+                      f"slab of the same input; {dt:.1f} s"}
+
+
+def profile_only(args, torch, mms, synth, grid, x, outs, sweeps, c_box4, c_box3, dev):
+    """Launch one kernel family repeatedly (for rocprofv3 runs)."""
+    k = args.only
+    out = outs["box4"]
+    if k in sweeps:
+        f = sweeps[k]
+    elif k.startswith("box4_") or k.startswith("box3_"):
+        r = 4 if k.startswith("box4") else 3
+        prec = k.split("_", 1)[1]
+        c = c_box4 if r == 4 else c_box3
+        f = lambda: mms.stencil_apply(x, out, grid, "box", r, c, precision=prec)
+    elif k == "copy":
+        f = lambda: out.copy_(x)
+    elif k == "wave":
+        n = 400
+        s = synth.wave_setup(n, 64, seed=7, sponge_width=32)
+        g4 = mms.Grid(n, n, n)
+        w = mms.Wave(g4, torch.from_numpy(s.c2).to(dev), LAP, 64, 1.0, s.sponge_width,
+                     s.sponge_alpha, s.sponge_faces, s.src,
+                     torch.from_numpy(s.src_dt2f).to(dev), None, None)
+        bufs = [g4.zeros(dev) for _ in range(3)]
+        it = [0]
+
+        def f():
+            i = it[0] % 60 + 1
+            w.step(i, bufs[(i - 1) % 3], bufs[i % 3], bufs[(i + 1) % 3])
+            it[0] += 1
+    else:
+        raise SystemExit(f"unknown --only {k}")
+    for _ in range(args.warmup):
+        f()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        f()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / args.steps
+    print(json.dumps({"only": k, "steps": args.steps, "ms_per_launch": ms}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

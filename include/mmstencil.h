@@ -1,0 +1,200 @@
+/*
+ * mmstencil.h -- C ABI of the MI355X (gfx950) high-order stencil library.
+ *
+ * The library computes the hot path of MMStencil (arXiv 2507.11067): sweeps of
+ * 3-D high-order FP32 stencils over a regular grid (the star and box patterns
+ * of the problem statement in Sec. I; radius 4 is the 8th-order case of
+ * Sec. II-A) and the acoustic wave time step those sweeps drive in reverse-time
+ * migration (Sec. II-A, Sec. V-F), with its exact discrete adjoint and the
+ * gradient of a receiver misfit with respect to C2 = (v dt / h)^2.
+ *
+ * Conventions shared by every entry point
+ *  - Grid and field pointers are DEVICE pointers owned by the caller.  The
+ *    library keeps no reference after a call returns.
+ *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*,
+ *    NULL = the default stream).  Errors found by the host-side checks are
+ *    returned before anything is enqueued; launch failures return MMS_EHIP.
+ *  - Return value 0 means success; negative values are the MMS_E* codes below.
+ *    No exception crosses the ABI.  Calls on different streams are thread-safe.
+ *  - Grid layout (mms_grid): FP32 elements, x fastest.  Interior point (z,y,x),
+ *    0 <= z < nz etc., is element (z+H)*sz + (y+H)*sy + (x+H) of the array.
+ *    Requirements (MMS_EINVAL otherwise): nx, ny, nz >= 0; H >= radius and
+ *    H % 4 == 0; sy % 4 == 0 and sy >= roundup4(nx) + 2H; sz % 4 == 0 and
+ *    sz >= sy * (ny + 2H); base pointer 16-byte aligned.  The array therefore
+ *    holds (nz + 2H) * sz elements.  Halo cells are read as stored and never
+ *    written; the workloads keep them zero (a zero-halo boundary).
+ *  - FP64 outputs (image, gradient) are dense interior arrays [nz][ny][nx].
+ */
+#ifndef MMSTENCIL_H
+#define MMSTENCIL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MMS_ABI_VERSION 1
+
+/* error codes */
+#define MMS_OK 0
+#define MMS_EINVAL (-1)       /* null pointer, bad layout, bad sizes, aliasing   */
+#define MMS_EUNSUPPORTED (-2) /* radius outside 1..4, split precision on a star  */
+#define MMS_EHIP (-3)         /* HIP runtime or launch error (see mms_last_error)*/
+#define MMS_ENOMEM (-4)       /* a library-owned buffer could not be allocated  */
+
+/* stencil shapes (Sec. I: star = axes only, box = full (2r+1)^3 cube) */
+#define MMS_STAR 0
+#define MMS_BOX 1
+
+/* arithmetic of a box sweep */
+#define MMS_FP32 0     /* FP32 FMA on the vector ALUs                                 */
+#define MMS_BF16X3 1   /* MFMA, BF16 hi+lo split of data and weights, 3 products,   */
+                       /* FP32 accumulation                                          */
+#define MMS_FP16X3S 2  /* MFMA, FP16 hi+lo split with a power-of-two scale per      */
+                       /* thread block (data) and per call (weights), 3 products    */
+#define MMS_BF16X1 3   /* MFMA, BF16 hi*hi only: reduced-accuracy reference variant  */
+
+typedef struct mms_grid {
+    int64_t nx, ny, nz; /* interior extent                                   */
+    int32_t halo;       /* H: halo width, >= radius, multiple of 4          */
+    int32_t pad_;       /* unused, keep 0                                   */
+    int64_t sy, sz;     /* element strides of y and z (x stride is 1)       */
+} mms_grid;
+
+/*
+ * mms_stencil_apply -- one out-of-place sweep, out = S(in) on the interior.
+ * Definition (Sec. I problem statement, Fig. 1 patterns):
+ *   star: out(p) = sum_{axis a} sum_{k=-r..r} coeffs[a][k+r] * in(p + k e_a),
+ *         coeffs is [3][2r+1] with axis order z, y, x (ncoeffs = 3(2r+1));
+ *   box:  out(p) = sum_{dz,dy,dx} coeffs[dz+r][dy+r][dx+r] * in(p + (dz,dy,dx)),
+ *         ncoeffs = (2r+1)^3.
+ * in, out: device grids with the same layout g; out's halo is not written; in
+ * and out must not overlap (MMS_EINVAL).  coeffs: HOST pointer, read during the
+ * call only.  radius: 1..4.  precision: MMS_FP32 for the star; any of the four
+ * for the box.  The box MFMA variants recast each (dz, dy) pair of the sweep as
+ * a banded Toeplitz product along x, the matrix-unit mapping of Sec. IV-A, with
+ * the (2r+1)^2 one-dimensional stencils of the box decomposition of Sec. IV-C.
+ */
+int mms_stencil_apply(const float *in, float *out, const mms_grid *g, int shape, int radius,
+                      const float *coeffs, int ncoeffs, int precision, void *stream);
+
+/*
+ * Acoustic problem description for the wave entry points.  The time step is
+ * the leapfrog update that RTM is built on (Sec. II-A), with an absorbing
+ * sponge G and a point source:
+ *   u^{n+1} = G (2 u^n - G u^{n-1} + C2 S(u^n)) + src_dt2f[n] delta_src
+ * S is the star with per-axis symmetric weights lap (unit spacing), C2 =
+ * (v dt / h)^2 = c2_scale * c2[cell].  G(z,y,x) = gz(z) gy(y) gx(x) with g(d) = exp(-(alpha (W-d))^2)
+ * for a cell at distance d < W from a damped face and 1 elsewhere.
+ */
+typedef struct mms_wave {
+    mms_grid g;
+    int32_t radius;       /* 1..4                                                   */
+    float lap[5];         /* per-axis weights: centre, then k = 1..radius           */
+    const float *c2;      /* device grid (layout g), zero halo: C2 = c2_scale * c2   */
+    float c2_scale;       /* 1 when c2 holds C2; dt^2 / h^2 when it holds v^2       */
+    int32_t sponge_width; /* W >= 0 cells                                           */
+    float sponge_alpha;   /* alpha                                                  */
+    int32_t sponge_faces; /* bit mask: 1 x-lo, 2 x-hi, 4 y-lo, 8 y-hi, 16 z-lo,     */
+                          /* 32 z-hi (z-lo is the top, z = 0)                       */
+    int32_t nt;           /* number of time levels 0..nt-1 recorded                 */
+    int64_t src_z, src_y, src_x; /* interior index of the point source              */
+    const float *src_dt2f;/* device [nt]: dt^2 f(n dt), or NULL for no source       */
+    float *traces;        /* device [nt][ny][nx]: d^n = u^n(z = 0), or NULL          */
+    double *image;        /* device [nz][ny][nx] FP64: += (u^{n+1})^2, or NULL       */
+} mms_wave;
+
+/*
+ * mms_wave_step -- one forward step n (1 <= n < nt): u_next = u^{n+1} from
+ * u_prev = u^{n-1}, u_cur = u^n; records traces[n] = u^n(z = 0) and adds
+ * (u^{n+1})^2 to image when those are set.  u_next may equal u_prev (the update
+ * reads and writes each cell in place); u_next must not overlap u_cur.
+ */
+int mms_wave_step(const mms_wave *w, int n, const float *u_prev, const float *u_cur,
+                  float *u_next, void *stream);
+
+/*
+ * mms_wave_record -- traces[n] = u(z = 0): the receiver reading of a level that
+ * no step produces from the recurrence (level 0).
+ */
+int mms_wave_record(const mms_wave *w, int n, const float *u, void *stream);
+
+/*
+ * mms_wave_forward -- steps n = n_begin .. n_end-1 in one call.
+ * states[i] holds u^{n_begin-1+i} for i = 0 .. n_end-n_begin+1: entries 0 and 1
+ * are inputs, the rest are outputs.  Entries may repeat (three buffers used in
+ * rotation, or two with u_next = u_prev) as long as step n never writes the
+ * buffer that holds u^n.  states is a HOST array of device pointers.
+ */
+int mms_wave_forward(const mms_wave *w, int n_begin, int n_end, float *const *states,
+                     void *stream);
+
+/*
+ * mms_wave_adjoint_step -- one step n of the exact discrete adjoint of the
+ * recurrence above (the transpose of the state map (u^n, u^{n-1}) ->
+ * (u^{n+1}, u^n); the paper has no adjoint).  For n >= 1:
+ *   lam^n = 2 G lam^{n+1} - G^2 lam^{n+2} + S^T(C2 G lam^{n+1}) + R^T resid[n]
+ *   grad += c2_scale G lam^{n+1} S(u^n)     (FP64, dense [nz][ny][nx])
+ * For n = 0: lam^0 = -G^2 lam^2 + R^T resid[0] (no gradient term).
+ * R^T adds resid[n] ([ny][nx], device, may be NULL) to the plane z = 0.  u_n is
+ * needed when grad is set and n >= 1.  lam_n may equal lam_np2.
+ * grad is dJ/d(c2 field): dJ/dC2 for c2_scale = 1, dJ/d(v^2) for c2_scale =
+ * dt^2 / h^2.
+ */
+int mms_wave_adjoint_step(const mms_wave *w, int n, const float *lam_np2, const float *lam_np1,
+                          float *lam_n, const float *resid, const float *u_n, double *grad,
+                          void *stream);
+
+/*
+ * mms_wave_adjoint -- adjoint steps n = n_hi down to n_lo in one call.
+ * lams[i] holds lam^{n_lo+i} for i = 0 .. n_hi-n_lo+2 (the last two are inputs);
+ * us[i] holds u^{n_lo+i} for i = 0 .. n_hi-n_lo (read for n >= 1 when grad is
+ * set).  resid is the whole [nt][ny][nx] residual (device) or NULL.  Both
+ * pointer arrays live on the host; entries may repeat as for mms_wave_forward.
+ */
+int mms_wave_adjoint(const mms_wave *w, int n_hi, int n_lo, float *const *lams,
+                     const float *const *us, const float *resid, double *grad, void *stream);
+
+/*
+ * mms_wave_energy -- FP64 discrete energy of the leapfrog scheme without
+ * sponge or source, E^{n+1/2} = sum (u^{n+1}-u^n)^2 / C2 - <u^{n+1}, S u^n>,
+ * which the scheme conserves exactly for a symmetric S.  *out_dev (device) is
+ * overwritten.  Cells with C2 == 0 add only the second term.
+ */
+int mms_wave_energy(const mms_wave *w, const float *u_n, const float *u_np1, double *out_dev,
+                    void *stream);
+
+/*
+ * FP64 reductions of FP32 data (fixed-shape two-level tree, no atomics, so a
+ * result is bit-reproducible).  Results are written to *out_dev (device).
+ *   mms_dot_f64:      sum over the interior of a*b (b == NULL: a*a)
+ *   mms_flat_dot_f64: sum_i a[i]*b[i] over n contiguous elements (b == NULL: a*a)
+ *   mms_flat_misfit_f64: 0.5 * sum_i (a[i]-b[i])^2, and resid[i] = a[i]-b[i]
+ *                     when resid is non-NULL (may equal a).
+ * The library keeps one small per-device buffer of partial sums for these
+ * (allocated on first use; MMS_ENOMEM if that fails).
+ */
+int mms_dot_f64(const float *a, const float *b, const mms_grid *g, double *out_dev, void *stream);
+int mms_flat_dot_f64(const float *a, const float *b, int64_t n, double *out_dev, void *stream);
+int mms_flat_misfit_f64(const float *a, const float *b, float *resid, int64_t n, double *out_dev,
+                        void *stream);
+
+/*
+ * mms_dense_to_grid -- out(z,y,x) = (float)(scale * in[z][y][x]) on the interior
+ * of a device grid (halo untouched); in is a dense FP64 device array.  Turns an
+ * FP64 gradient into the layout of the field it belongs to.
+ */
+int mms_dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, void *stream);
+
+/* Tuning of the star and box launches (z-chunk length; 0 = automatic). */
+int mms_set_zchunk(int shape, int precision, int zchunk);
+
+const char *mms_strerror(int code);
+const char *mms_last_error(void); /* text of the last MMS_EHIP on this thread */
+int mms_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMSTENCIL_H */

@@ -59,6 +59,9 @@ def _load():
         wp = ctypes.POINTER(_Wave)
         lib.orc_star.argtypes = [_dp, _dp, gp, ctypes.c_int, _dp]
         lib.orc_box.argtypes = [_dp, _dp, gp, ctypes.c_int, _dp]
+        lp = ctypes.POINTER(ctypes.c_long)
+        lib.orc_star_at.argtypes = [_dp, gp, ctypes.c_int, _dp, ctypes.c_long, lp, _dp]
+        lib.orc_box_at.argtypes = [_dp, gp, ctypes.c_int, _dp, ctypes.c_long, lp, _dp]
         lib.orc_sponge_1d.argtypes = [ctypes.c_long, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, _dp]
         lib.orc_wave_step.argtypes = [wp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
@@ -107,6 +110,32 @@ def box(inp: np.ndarray, nx: int, ny: int, nz: int, radius: int, coeffs,
     g = _grid(a, nx, ny, nz, halo)
     _load().orc_box(_ptr(a), _ptr(out), ctypes.byref(g), radius, _ptr(c))
     return out
+
+
+def _at(fn, inp, nx, ny, nz, radius, coeffs, points, halo, shape):
+    a = inp if (inp.dtype == np.float64 and inp.flags.c_contiguous) else None
+    if a is None:
+        raise ValueError("sampled evaluation needs a contiguous FP64 grid (convert once, reuse)")
+    pts = np.ascontiguousarray(points, dtype=np.int64).reshape(-1, 3)
+    assert np.all(pts >= 0) and np.all(pts < np.array([nz, ny, nx]))
+    c = _f64(np.asarray(coeffs).reshape(shape))
+    out = np.zeros(len(pts))
+    g = _grid(a, nx, ny, nz, halo)
+    fn(_ptr(a), ctypes.byref(g), radius, _ptr(c), len(pts),
+       pts.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _ptr(out))
+    return out
+
+
+def star_at(inp, nx, ny, nz, radius, coeffs, points, halo=4):
+    """Star definition at the interior points [(z, y, x), ...] of an FP64 padded grid."""
+    return _at(_load().orc_star_at, inp, nx, ny, nz, radius, coeffs, points, halo,
+               (3, 2 * radius + 1))
+
+
+def box_at(inp, nx, ny, nz, radius, coeffs, points, halo=4):
+    """Box definition at the interior points [(z, y, x), ...] of an FP64 padded grid."""
+    n = 2 * radius + 1
+    return _at(_load().orc_box_at, inp, nx, ny, nz, radius, coeffs, points, halo, (n, n, n))
 
 
 def sponge_1d(n: int, width: int, alpha: float, damp_lo: bool, damp_hi: bool) -> np.ndarray:

@@ -75,6 +75,40 @@ void orc_box(const double *in, double *out, const orc_grid *g, int r, const doub
             }
 }
 
+/* The same two definitions evaluated at a list of interior points only
+ * (pts holds npts (z, y, x) triples); used to check sampled outputs of large
+ * grids without sweeping the whole grid. */
+void orc_star_at(const double *in, const orc_grid *g, int r, const double *c, long npts,
+                 const long *pts, double *out) {
+    const int w = 2 * r + 1;
+    const double *cz = c, *cy = c + w, *cx = c + 2 * w;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < npts; ++i) {
+        const long z = pts[3 * i], y = pts[3 * i + 1], x = pts[3 * i + 2];
+        double s = 0.0;
+        for (int k = -r; k <= r; ++k) s += cz[k + r] * in[at(g, z + k, y, x)];
+        for (int k = -r; k <= r; ++k) s += cy[k + r] * in[at(g, z, y + k, x)];
+        for (int k = -r; k <= r; ++k) s += cx[k + r] * in[at(g, z, y, x + k)];
+        out[i] = s;
+    }
+}
+
+void orc_box_at(const double *in, const orc_grid *g, int r, const double *c, long npts,
+                const long *pts, double *out) {
+    const int w = 2 * r + 1;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < npts; ++i) {
+        const long z = pts[3 * i], y = pts[3 * i + 1], x = pts[3 * i + 2];
+        double s = 0.0;
+        for (int dz = -r; dz <= r; ++dz)
+            for (int dy = -r; dy <= r; ++dy)
+                for (int dx = -r; dx <= r; ++dx)
+                    s += c[((dz + r) * w + (dy + r)) * w + (dx + r)] *
+                         in[at(g, z + dz, y + dy, x + dx)];
+        out[i] = s;
+    }
+}
+
 /* Transpose of the star operator on the interior (zero outside it):
  * out(q) = sum_{a,k} c[a][k+r] * in(q - k e_a), with in read as 0 off the interior. */
 static void star_transpose(const double *in, double *out, const orc_grid *g, int r,

@@ -1,0 +1,245 @@
+"""MI355X (gfx950) library for the MMStencil hot path: 3-D high-order stencil
+sweeps (star and box, radius 1..4) and the acoustic wave step they drive, with
+its exact adjoint and gradient.
+
+This module only marshals arguments for the C ABI of libmmstencil.so (declared
+in include/mmstencil.h).  PyTorch supplies device memory and the current HIP
+stream; every arithmetic step runs in the library's HIP kernels.  There is no
+CPU fallback: if the library is not built, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import (MMS_BF16X1, MMS_BF16X3, MMS_BOX, MMS_FP16X3S, MMS_FP32, MMS_STAR, MmsError,
+                   check, lib)
+
+__all__ = ["Grid", "stencil_apply", "Wave", "dot", "flat_dot", "flat_misfit", "dense_to_grid",
+           "set_zchunk", "MmsError", "PRECISIONS", "SHAPES"]
+
+PRECISIONS = {"fp32": MMS_FP32, "bf16x3": MMS_BF16X3, "fp16x3s": MMS_FP16X3S, "bf16x1": MMS_BF16X1}
+SHAPES = {"star": MMS_STAR, "box": MMS_BOX}
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Padded FP32 grid layout: interior (z, y, x) at [z+H][y+H][x+H] of a
+    (nz+2H, ny+2H, sy) array, x fastest."""
+    nx: int
+    ny: int
+    nz: int
+    halo: int = 4
+    sy: int | None = None
+
+    def __post_init__(self):
+        if self.sy is None:
+            need = ((self.nx + 3) // 4) * 4 + 2 * self.halo
+            object.__setattr__(self, "sy", ((need + 3) // 4) * 4)
+
+    @property
+    def shape(self):
+        return (self.nz + 2 * self.halo, self.ny + 2 * self.halo, self.sy)
+
+    @property
+    def sz(self):
+        return (self.ny + 2 * self.halo) * self.sy
+
+    @property
+    def points(self):
+        return self.nx * self.ny * self.nz
+
+    def c(self) -> _lib.MmsGrid:
+        return _lib.MmsGrid(self.nx, self.ny, self.nz, self.halo, 0, self.sy, self.sz)
+
+    def zeros(self, device="cuda", dtype=torch.float32) -> torch.Tensor:
+        return torch.zeros(self.shape, device=device, dtype=dtype)
+
+    def interior(self, t: torch.Tensor) -> torch.Tensor:
+        H = self.halo
+        return t[H:H + self.nz, H:H + self.ny, H:H + self.nx]
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _grid_ptr(t: torch.Tensor | None, grid: Grid, name: str, dtype=torch.float32):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor")
+    if tuple(t.shape) != grid.shape:
+        raise ValueError(f"{name}: shape {tuple(t.shape)} does not match grid {grid.shape}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_ptr(t: torch.Tensor | None, name: str, dtype, numel: int | None = None):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name}: need a contiguous {dtype} CUDA tensor")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: needs {numel} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def stencil_apply(inp: torch.Tensor, out: torch.Tensor, grid: Grid, shape: str, radius: int,
+                  coeffs, precision: str = "fp32", stream=None) -> torch.Tensor:
+    """One sweep out = S(inp) (star or box, radius 1..4), see mms_stencil_apply."""
+    c = torch.as_tensor(coeffs, dtype=torch.float32).detach().cpu().contiguous().reshape(-1)
+    g = grid.c()
+    rc = lib().mms_stencil_apply(_grid_ptr(inp, grid, "inp"), _grid_ptr(out, grid, "out"),
+                                 ctypes.byref(g), SHAPES[shape], int(radius),
+                                 ctypes.cast(c.data_ptr(), ctypes.POINTER(ctypes.c_float)),
+                                 c.numel(), PRECISIONS[precision], _stream(stream))
+    check(rc, "mms_stencil_apply")
+    return out
+
+
+def set_zchunk(shape: str, precision: str, zchunk: int) -> None:
+    check(lib().mms_set_zchunk(SHAPES[shape], PRECISIONS[precision], int(zchunk)), "mms_set_zchunk")
+
+
+class Wave:
+    """Acoustic problem (mms_wave) bound to device tensors.
+
+    c2: padded grid tensor; C2 = c2_scale * c2 (c2_scale = 1 for a C2 field,
+    dt^2/h^2 for a v^2 field).  src_dt2f: device [nt] FP32 or None.
+    traces: device [nt, ny, nx] FP32 or None.  image: device [nz, ny, nx] FP64 or None.
+    """
+
+    def __init__(self, grid: Grid, c2: torch.Tensor, lap, nt: int, c2_scale: float = 1.0,
+                 sponge_width: int = 0, sponge_alpha: float = 0.0, sponge_faces: int = 0,
+                 src=(0, 0, 0), src_dt2f: torch.Tensor | None = None,
+                 traces: torch.Tensor | None = None, image: torch.Tensor | None = None):
+        self.grid = grid
+        self.c2 = c2
+        self.src_dt2f = src_dt2f
+        self.traces = traces
+        self.image = image
+        self.nt = nt
+        lapf = (ctypes.c_float * 5)(*([float(v) for v in lap] + [0.0] * (5 - len(lap))))
+        self._w = _lib.MmsWave(grid.c(), len(lap) - 1, lapf, _grid_ptr(c2, grid, "c2"),
+                               float(c2_scale), int(sponge_width), float(sponge_alpha),
+                               int(sponge_faces), int(nt), int(src[0]), int(src[1]), int(src[2]),
+                               _dev_ptr(src_dt2f, "src_dt2f", torch.float32, nt),
+                               _dev_ptr(traces, "traces", torch.float32, nt * grid.ny * grid.nx),
+                               _dev_ptr(image, "image", torch.float64, grid.points))
+
+    def set_c2(self, c2: torch.Tensor, c2_scale: float | None = None):
+        self.c2 = c2
+        self._w.c2 = _grid_ptr(c2, self.grid, "c2")
+        if c2_scale is not None:
+            self._w.c2_scale = float(c2_scale)
+
+    def set_traces(self, traces: torch.Tensor | None):
+        self.traces = traces
+        self._w.traces = _dev_ptr(traces, "traces", torch.float32,
+                                  self.nt * self.grid.ny * self.grid.nx)
+
+    def set_image(self, image: torch.Tensor | None):
+        self.image = image
+        self._w.image = _dev_ptr(image, "image", torch.float64, self.grid.points)
+
+    def set_source(self, src_dt2f: torch.Tensor | None, src=None):
+        self.src_dt2f = src_dt2f
+        self._w.src_dt2f = _dev_ptr(src_dt2f, "src_dt2f", torch.float32, self.nt)
+        if src is not None:
+            self._w.src_z, self._w.src_y, self._w.src_x = (int(v) for v in src)
+
+    def step(self, n, u_prev, u_cur, u_next, stream=None):
+        g = self.grid
+        check(lib().mms_wave_step(ctypes.byref(self._w), int(n), _grid_ptr(u_prev, g, "u_prev"),
+                                  _grid_ptr(u_cur, g, "u_cur"), _grid_ptr(u_next, g, "u_next"),
+                                  _stream(stream)), "mms_wave_step")
+
+    def record(self, n, u, stream=None):
+        check(lib().mms_wave_record(ctypes.byref(self._w), int(n), _grid_ptr(u, self.grid, "u"),
+                                    _stream(stream)), "mms_wave_record")
+
+    def forward(self, n_begin, n_end, states, stream=None):
+        """Steps n_begin..n_end-1; states[i] is u^{n_begin-1+i} (see mms_wave_forward)."""
+        arr = (ctypes.c_void_p * len(states))(*[_grid_ptr(s, self.grid, "state") for s in states])
+        if len(states) < n_end - n_begin + 2:
+            raise ValueError("states too short")
+        check(lib().mms_wave_forward(ctypes.byref(self._w), int(n_begin), int(n_end), arr,
+                                     _stream(stream)), "mms_wave_forward")
+
+    def adjoint_step(self, n, lam_np2, lam_np1, lam_n, resid=None, u_n=None, grad=None,
+                     stream=None):
+        g = self.grid
+        check(lib().mms_wave_adjoint_step(
+            ctypes.byref(self._w), int(n), _grid_ptr(lam_np2, g, "lam_np2"),
+            _grid_ptr(lam_np1, g, "lam_np1"), _grid_ptr(lam_n, g, "lam_n"),
+            _dev_ptr(resid, "resid", torch.float32, self.nt * g.ny * g.nx),
+            _grid_ptr(u_n, g, "u_n"), _dev_ptr(grad, "grad", torch.float64, g.points),
+            _stream(stream)), "mms_wave_adjoint_step")
+
+    def adjoint(self, n_hi, n_lo, lams, us=None, resid=None, grad=None, stream=None):
+        """Adjoint steps n_hi..n_lo; lams[i] is lam^{n_lo+i}, us[i] is u^{n_lo+i}."""
+        g = self.grid
+        if len(lams) < n_hi - n_lo + 3:
+            raise ValueError("lams too short")
+        la = (ctypes.c_void_p * len(lams))(*[_grid_ptr(t, g, "lam") for t in lams])
+        ua = None
+        if us is not None:
+            ua = (ctypes.c_void_p * len(us))(*[_grid_ptr(t, g, "u") for t in us])
+        check(lib().mms_wave_adjoint(
+            ctypes.byref(self._w), int(n_hi), int(n_lo), la, ua,
+            _dev_ptr(resid, "resid", torch.float32, self.nt * g.ny * g.nx),
+            _dev_ptr(grad, "grad", torch.float64, g.points), _stream(stream)), "mms_wave_adjoint")
+
+    def energy(self, u_n, u_np1, stream=None) -> float:
+        out = torch.zeros(1, dtype=torch.float64, device=u_n.device)
+        check(lib().mms_wave_energy(ctypes.byref(self._w), _grid_ptr(u_n, self.grid, "u_n"),
+                                    _grid_ptr(u_np1, self.grid, "u_np1"),
+                                    _dev_ptr(out, "out", torch.float64), _stream(stream)),
+              "mms_wave_energy")
+        return float(out.item())
+
+
+def dot(a: torch.Tensor, b: torch.Tensor | None, grid: Grid, stream=None) -> float:
+    out = torch.zeros(1, dtype=torch.float64, device=a.device)
+    g = grid.c()
+    check(lib().mms_dot_f64(_grid_ptr(a, grid, "a"), _grid_ptr(b, grid, "b"), ctypes.byref(g),
+                            _dev_ptr(out, "out", torch.float64), _stream(stream)), "mms_dot_f64")
+    return float(out.item())
+
+
+def flat_dot(a: torch.Tensor, b: torch.Tensor | None = None, stream=None) -> float:
+    out = torch.zeros(1, dtype=torch.float64, device=a.device)
+    n = a.numel()
+    check(lib().mms_flat_dot_f64(_dev_ptr(a, "a", torch.float32), _dev_ptr(b, "b", torch.float32, n),
+                                 n, _dev_ptr(out, "out", torch.float64), _stream(stream)),
+          "mms_flat_dot_f64")
+    return float(out.item())
+
+
+def flat_misfit(a: torch.Tensor, b: torch.Tensor, resid: torch.Tensor | None = None,
+                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """0.5 * sum (a - b)^2 in FP64 on the device (returned as a 1-element tensor);
+    writes resid = a - b when given."""
+    if out is None:
+        out = torch.zeros(1, dtype=torch.float64, device=a.device)
+    n = a.numel()
+    check(lib().mms_flat_misfit_f64(_dev_ptr(a, "a", torch.float32),
+                                    _dev_ptr(b, "b", torch.float32, n),
+                                    _dev_ptr(resid, "resid", torch.float32, n), n,
+                                    _dev_ptr(out, "out", torch.float64), _stream(stream)),
+          "mms_flat_misfit_f64")
+    return out
+
+
+def dense_to_grid(dense: torch.Tensor, out: torch.Tensor, grid: Grid, scale: float = 1.0,
+                  stream=None) -> torch.Tensor:
+    g = grid.c()
+    check(lib().mms_dense_to_grid(_dev_ptr(dense, "dense", torch.float64, grid.points),
+                                  _grid_ptr(out, grid, "out"), ctypes.byref(g), float(scale),
+                                  _stream(stream)), "mms_dense_to_grid")
+    return out

@@ -1,0 +1,259 @@
+// C ABI of libmmstencil: argument checks, dispatch and error reporting.
+// Every check runs on the host before any HIP call, so it is testable without
+// a GPU.
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "mms_internal.h"
+
+namespace mms {
+
+int wave_step(const mms_wave *w, int n, const float *up, const float *uc, float *un, hipStream_t s);
+int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1, float *l0,
+                      const float *resid, const float *un, double *grad, hipStream_t s);
+int wave_record(const mms_wave *w, int n, const float *u, hipStream_t s);
+int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *out, double *partials,
+                int64_t npartials, hipStream_t s);
+int64_t wave_energy_blocks(const mms_wave *w);
+int dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, hipStream_t s);
+int reduce_grid_dot(const float *a, const float *b, const mms_grid *g, double *out, double *part,
+                    hipStream_t s);
+int reduce_flat(const float *a, const float *b, float *resid, int64_t n, int misfit, double *out,
+                double *part, hipStream_t s);
+int reduce_partials_count();
+
+namespace {
+thread_local char g_last[256] = "";
+int g_zchunk[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+
+// per-device buffer of FP64 partial sums used by the reductions
+constexpr int kMaxDev = 64;
+constexpr int64_t kPartials = 1 << 16;
+double *g_partials[kMaxDev] = {};
+std::mutex g_mu;
+
+int partials(double **p) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDev) return MMS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_partials[dev]) {
+        e = hipMalloc((void **)&g_partials[dev], kPartials * sizeof(double));
+        if (e != hipSuccess) {
+            g_partials[dev] = nullptr;
+            snprintf(g_last, sizeof g_last, "hipMalloc of the partial-sum buffer: %s",
+                     hipGetErrorString(e));
+            return MMS_ENOMEM;
+        }
+    }
+    *p = g_partials[dev];
+    return MMS_OK;
+}
+}  // namespace
+
+int hip_fail(hipError_t e, const char *where) {
+    snprintf(g_last, sizeof g_last, "%s: %s", where, hipGetErrorString(e));
+    return MMS_EHIP;
+}
+
+int check_launch(const char *where) {
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MMS_OK : hip_fail(e, where);
+}
+
+bool grid_ok(const mms_grid *g, int radius) {
+    if (!g) return false;
+    if (g->nx < 0 || g->ny < 0 || g->nz < 0) return false;
+    if (g->nx > (1 << 30) || g->ny > (1 << 30) || g->nz > (1 << 30)) return false;
+    if (g->halo < radius || g->halo < 4 || g->halo % 4 != 0) return false;
+    const int64_t nx4 = (g->nx + 3) & ~(int64_t)3;
+    if (g->sy % 4 != 0 || g->sy < nx4 + 2 * (int64_t)g->halo) return false;
+    if (g->sz % 4 != 0 || g->sz < g->sy * (g->ny + 2 * (int64_t)g->halo)) return false;
+    return true;
+}
+
+bool overlap(const void *a, int64_t abytes, const void *b, int64_t bbytes) {
+    const char *pa = (const char *)a, *pb = (const char *)b;
+    return pa < pb + bbytes && pb < pa + abytes;
+}
+
+int zchunk_override(int shape, int precision) {
+    if (shape < 0 || shape > 1 || precision < 0 || precision > 3) return 0;
+    return g_zchunk[shape][precision];
+}
+
+}  // namespace mms
+
+using namespace mms;
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+extern "C" {
+
+int mms_abi_version(void) { return MMS_ABI_VERSION; }
+
+const char *mms_strerror(int code) {
+    switch (code) {
+        case MMS_OK: return "ok";
+        case MMS_EINVAL: return "invalid argument";
+        case MMS_EUNSUPPORTED: return "unsupported radius, shape or precision";
+        case MMS_EHIP: return "HIP runtime error";
+        case MMS_ENOMEM: return "out of device memory";
+        default: return "unknown error";
+    }
+}
+
+const char *mms_last_error(void) { return g_last; }
+
+int mms_set_zchunk(int shape, int precision, int zchunk) {
+    if (shape < 0 || shape > 1 || precision < 0 || precision > 3 || zchunk < 0) return MMS_EINVAL;
+    g_zchunk[shape][precision] = zchunk;
+    return MMS_OK;
+}
+
+int mms_stencil_apply(const float *in, float *out, const mms_grid *g, int shape, int radius,
+                      const float *coeffs, int ncoeffs, int precision, void *stream) {
+    if (radius < 1 || radius > 4) return MMS_EUNSUPPORTED;
+    if (shape != MMS_STAR && shape != MMS_BOX) return MMS_EUNSUPPORTED;
+    if (precision < MMS_FP32 || precision > MMS_BF16X1) return MMS_EUNSUPPORTED;
+    if (shape == MMS_STAR && precision != MMS_FP32) return MMS_EUNSUPPORTED;
+    if (!in || !out || !coeffs || !g) return MMS_EINVAL;
+    if (!grid_ok(g, radius)) return MMS_EINVAL;
+    if (!aligned16(in) || !aligned16(out)) return MMS_EINVAL;
+    const int w = 2 * radius + 1;
+    if (ncoeffs != (shape == MMS_STAR ? 3 * w : w * w * w)) return MMS_EINVAL;
+    const int64_t bytes = grid_elems(g) * (int64_t)sizeof(float);
+    if (overlap(in, bytes, out, bytes)) return MMS_EINVAL;
+    if (grid_empty(g)) return MMS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (shape == MMS_STAR) return launch_star(in, out, g, radius, coeffs, s);
+    if (precision == MMS_FP32) return launch_box_valu(in, out, g, radius, coeffs, s);
+    return launch_box_mfma(in, out, g, radius, coeffs, precision, s);
+}
+
+static int wave_ok(const mms_wave *w) {
+    if (!w) return MMS_EINVAL;
+    if (w->radius < 1 || w->radius > 4) return MMS_EUNSUPPORTED;
+    if (!grid_ok(&w->g, w->radius) || !w->c2 || !aligned16(w->c2)) return MMS_EINVAL;
+    if (w->sponge_width < 0 || w->nt < 0) return MMS_EINVAL;
+    if (w->src_dt2f && (w->src_z < 0 || w->src_z >= w->g.nz || w->src_y < 0 ||
+                        w->src_y >= w->g.ny || w->src_x < 0 || w->src_x >= w->g.nx))
+        return MMS_EINVAL;
+    return MMS_OK;
+}
+
+int mms_wave_step(const mms_wave *w, int n, const float *u_prev, const float *u_cur, float *u_next,
+                  void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!u_prev || !u_cur || !u_next) return MMS_EINVAL;
+    if (!aligned16(u_prev) || !aligned16(u_cur) || !aligned16(u_next)) return MMS_EINVAL;
+    if (n < 1 || n >= w->nt) return MMS_EINVAL;
+    const int64_t bytes = grid_elems(&w->g) * (int64_t)sizeof(float);
+    if (overlap(u_cur, bytes, u_next, bytes)) return MMS_EINVAL;
+    if (u_prev != u_next && overlap(u_prev, bytes, u_next, bytes)) return MMS_EINVAL;
+    if (grid_empty(&w->g)) return MMS_OK;
+    return wave_step(w, n, u_prev, u_cur, u_next, (hipStream_t)stream);
+}
+
+int mms_wave_record(const mms_wave *w, int n, const float *u, void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!u || !w->traces || n < 0 || n >= w->nt) return MMS_EINVAL;
+    if (grid_empty(&w->g)) return MMS_OK;
+    return wave_record(w, n, u, (hipStream_t)stream);
+}
+
+int mms_wave_forward(const mms_wave *w, int n_begin, int n_end, float *const *states, void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!states || n_begin < 1 || n_end > w->nt || n_end < n_begin) return MMS_EINVAL;
+    const int64_t bytes = grid_elems(&w->g) * (int64_t)sizeof(float);
+    for (int n = n_begin; n < n_end; ++n) {
+        const int i = n - n_begin;  // states[i] = u^{n-1}, states[i+1] = u^n, states[i+2] = u^{n+1}
+        float *up = states[i], *uc = states[i + 1], *un = states[i + 2];
+        if (!up || !uc || !un) return MMS_EINVAL;
+        if (overlap(uc, bytes, un, bytes)) return MMS_EINVAL;
+        if (up != un && overlap(up, bytes, un, bytes)) return MMS_EINVAL;
+    }
+    for (int n = n_begin; n < n_end; ++n) {
+        const int i = n - n_begin;
+        if (int rc = mms_wave_step(w, n, states[i], states[i + 1], states[i + 2], stream)) return rc;
+    }
+    return MMS_OK;
+}
+
+int mms_wave_adjoint_step(const mms_wave *w, int n, const float *lam_np2, const float *lam_np1,
+                          float *lam_n, const float *resid, const float *u_n, double *grad,
+                          void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (n < 0 || n >= w->nt || !lam_np2 || !lam_n) return MMS_EINVAL;
+    if (n >= 1 && !lam_np1) return MMS_EINVAL;
+    if (n >= 1 && grad && !u_n) return MMS_EINVAL;
+    const int64_t bytes = grid_elems(&w->g) * (int64_t)sizeof(float);
+    if (lam_np1 && overlap(lam_np1, bytes, lam_n, bytes)) return MMS_EINVAL;
+    if (lam_np2 != lam_n && overlap(lam_np2, bytes, lam_n, bytes)) return MMS_EINVAL;
+    if (u_n && overlap(u_n, bytes, lam_n, bytes)) return MMS_EINVAL;
+    if (grid_empty(&w->g)) return MMS_OK;
+    return wave_adjoint_step(w, n, lam_np2, lam_np1, lam_n, resid, u_n, grad, (hipStream_t)stream);
+}
+
+int mms_wave_adjoint(const mms_wave *w, int n_hi, int n_lo, float *const *lams,
+                     const float *const *us, const float *resid, double *grad, void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!lams || n_lo < 0 || n_hi >= w->nt || n_hi < n_lo) return MMS_EINVAL;
+    if (grad && !us) return MMS_EINVAL;
+    for (int n = n_hi; n >= n_lo; --n) {
+        const int i = n - n_lo;  // lams[i] = lam^n, lams[i+1] = lam^{n+1}, lams[i+2] = lam^{n+2}
+        const float *un = (grad && n >= 1) ? us[i] : nullptr;
+        const float *rs = resid;
+        int rc = mms_wave_adjoint_step(w, n, lams[i + 2], lams[i + 1], lams[i], rs, un, grad, stream);
+        if (rc) return rc;
+    }
+    return MMS_OK;
+}
+
+int mms_wave_energy(const mms_wave *w, const float *u_n, const float *u_np1, double *out_dev,
+                    void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!u_n || !u_np1 || !out_dev) return MMS_EINVAL;
+    double *part = nullptr;
+    if (int rc = partials(&part)) return rc;
+    if (wave_energy_blocks(w) > kPartials) return MMS_EINVAL;
+    if (grid_empty(&w->g)) {
+        hipError_t e = hipMemsetAsync(out_dev, 0, sizeof(double), (hipStream_t)stream);
+        return e == hipSuccess ? MMS_OK : hip_fail(e, "hipMemsetAsync");
+    }
+    return wave_energy(w, u_n, u_np1, out_dev, part, kPartials, (hipStream_t)stream);
+}
+
+int mms_dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, void *stream) {
+    if (!in || !out || !grid_ok(g, 1)) return MMS_EINVAL;
+    if (g->ny > 65535 || g->nz > 65535) return MMS_EINVAL;
+    if (grid_empty(g)) return MMS_OK;
+    return dense_to_grid(in, out, g, scale, (hipStream_t)stream);
+}
+
+int mms_dot_f64(const float *a, const float *b, const mms_grid *g, double *out_dev, void *stream) {
+    if (!a || !out_dev || !grid_ok(g, 1)) return MMS_EINVAL;
+    double *part = nullptr;
+    if (int rc = partials(&part)) return rc;
+    return reduce_grid_dot(a, b, g, out_dev, part, (hipStream_t)stream);
+}
+
+int mms_flat_dot_f64(const float *a, const float *b, int64_t n, double *out_dev, void *stream) {
+    if (!a || !out_dev || n < 0) return MMS_EINVAL;
+    double *part = nullptr;
+    if (int rc = partials(&part)) return rc;
+    return reduce_flat(a, b, nullptr, n, 0, out_dev, part, (hipStream_t)stream);
+}
+
+int mms_flat_misfit_f64(const float *a, const float *b, float *resid, int64_t n, double *out_dev,
+                        void *stream) {
+    if (!a || !b || !out_dev || n < 0) return MMS_EINVAL;
+    double *part = nullptr;
+    if (int rc = partials(&part)) return rc;
+    return reduce_flat(a, b, resid, n, 1, out_dev, part, (hipStream_t)stream);
+}
+
+}  // extern "C"

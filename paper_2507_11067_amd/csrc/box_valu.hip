@@ -1,0 +1,187 @@
+// Box-stencil sweep on the vector ALUs, FP32 FMA (radius 1..4).
+//
+// out(p) = sum_{dz,dy,dx in [-r,r]} c[dz][dy][dx] in(p + (dz,dy,dx))   (Sec. I)
+//
+// With (2r+1)^3 FMAs per point the box is bound by the FP32 FMA rate.  The
+// kernel follows the box decomposition of Sec. IV-C: the box is (2r+1)^2
+// one-dimensional x stencils, one per (dz, dy) pair, and each loaded input row
+// feeds all of them before it is dropped:
+//  * a block owns a (4*TX) x TY tile and streams z; one input plane of the tile
+//    (plus 4 cells of x halo and r rows of y halo) sits in LDS at a time,
+//    double-buffered, one barrier per plane;
+//  * each lane owns 4 consecutive x of one row and keeps 2r+1 partial sums for
+//    the 2r+1 output planes the current input plane feeds (input plane z'
+//    contributes to output z'-dz through weights c[dz]); the oldest sum is
+//    complete after each plane and the window shifts by one;
+//  * a lane reads 12 consecutive cells of one input row (three 16-byte LDS
+//    words) and applies all (2r+1) x (2r+1) weights of that dy to them, so LDS
+//    traffic is 3 words per (2r+1)^2 * 4 FMAs; the weights are uniform and come
+//    from the kernel-argument segment through the scalar unit.
+#include "mms_internal.h"
+
+namespace mms {
+namespace {
+
+struct BoxArgs {
+    Geom g;
+    float c[729];  // [dz][dy][dx] for radius r, (2r+1)^3 used
+};
+
+template <int R, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
+    constexpr int W = 2 * R + 1;
+    constexpr int BX = 4 * TX;
+    constexpr int BY = TY;
+    constexpr int LW4 = TX + 2;
+    constexpr int LH = BY + 2 * R;
+    constexpr int NT = TX * TY;
+    constexpr int NL = LW4 * LH;              // float4 per plane tile
+    constexpr int NLK = (NL + NT - 1) / NT;
+    __shared__ float4 tile[2][LH][LW4];
+
+    const Geom &g = a.g;
+    int b = mms_xcd_remap(blockIdx.x, gridDim.x);
+    const int txi = b % g.ntx;
+    b /= g.ntx;
+    const int tyi = b % g.nty;
+    const int zci = b / g.nty;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int xt = txi * BX, yt = tyi * BY;
+    const int x0 = xt + 4 * tx, y = yt + ty;
+    const int zb = zci * g.zchunk;
+    const int ze = min(zb + g.zchunk, g.nz);
+    const int nx4 = (g.nx + 3) & ~3;
+    const int ylim = g.ny + g.H;
+    const int64_t sy = g.sy, sz = g.sz;
+
+    // cooperative tile load: item i -> (row, col4) of the tile
+    int64_t l_off[NLK];
+    bool l_ok[NLK];
+#pragma unroll
+    for (int k = 0; k < NLK; ++k) {
+        const int i = tid + k * NT;
+        const int row = i / LW4, col = i % LW4;
+        const int yy = yt - R + row, xx = xt - 4 + 4 * col;
+        l_ok[k] = (i < NL) && (yy < ylim) && (xx <= nx4);
+        l_off[k] = (int64_t)yy * sy + xx;
+    }
+    float4 stage[NLK];
+    auto load_plane = [&](int z) {
+        const float *p = g.in0 + (int64_t)z * sz;
+#pragma unroll
+        for (int k = 0; k < NLK; ++k)
+            stage[k] = guarded_load(p + l_off[k], l_ok[k], g.in0);
+    };
+    auto store_plane = [&](int buf) {
+        float4 *t = &tile[buf][0][0];
+#pragma unroll
+        for (int k = 0; k < NLK; ++k)
+            if (tid + k * NT < NL) t[tid + k * NT] = stage[k];
+    };
+
+    float acc[W][4];
+#pragma unroll
+    for (int s = 0; s < W; ++s)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[s][e] = 0.f;
+
+    const int z_first = zb - R, z_last = ze + R;  // input planes [z_first, z_last)
+    load_plane(z_first);
+    store_plane(0);
+    __syncthreads();
+    int buf = 0;
+    for (int zi = z_first; zi < z_last; ++zi) {
+        const bool more = zi + 1 < z_last;
+        if (more) load_plane(zi + 1);
+        const float4 *t = &tile[buf][0][0];
+        for (int dy = -R; dy <= R; ++dy) {
+            const float4 *row = t + (ty + R + dy) * LW4;
+            const float4 L = row[tx], C = row[tx + 1], Rr = row[tx + 2];
+            const float w[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w, Rr.x, Rr.y, Rr.z, Rr.w};
+            const float *cdy = a.c + (dy + R) * W;
+#pragma unroll
+            for (int dz = -R; dz <= R; ++dz) {
+                const int zo = zi - dz;  // output plane fed through c[dz]
+                if (zo < zb || zo >= ze) continue;
+                const float *cc = cdy + (dz + R) * W * W;
+#pragma unroll
+                for (int dx = -R; dx <= R; ++dx) {
+                    const float ck = cc[dx + R];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[R - dz][e] = fmaf(ck, w[4 + e + dx], acc[R - dz][e]);
+                }
+            }
+        }
+        // output plane zi - R is complete
+        const int zo = zi - R;
+        if (zo >= zb && y < g.ny && x0 < g.nx) {
+            float *po = g.out0 + (int64_t)zo * sz + (int64_t)y * sy + x0;
+            if (x0 + 3 < g.nx) {
+                *reinterpret_cast<float4 *>(po) =
+                    make_float4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (x0 + e < g.nx) po[e] = acc[0][e];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s + 1 < W; ++s)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[s][e] = acc[s + 1][e];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[W - 1][e] = 0.f;
+        if (more) store_plane(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    (void)ylim;
+}
+
+template <int R>
+int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeffs, hipStream_t s) {
+    constexpr int TX = 16, TY = 16;
+    constexpr int W = 2 * R + 1;
+    BoxArgs a{};
+    Geom &g = a.g;
+    g.H = gd->halo;
+    g.in0 = in + (int64_t)g.H * (gd->sz + gd->sy + 1);
+    g.out0 = out + (int64_t)g.H * (gd->sz + gd->sy + 1);
+    g.nx = (int)gd->nx;
+    g.ny = (int)gd->ny;
+    g.nz = (int)gd->nz;
+    g.sy = gd->sy;
+    g.sz = gd->sz;
+    g.ntx = (g.nx + 4 * TX - 1) / (4 * TX);
+    g.nty = (g.ny + TY - 1) / TY;
+    int zc = zchunk_override(MMS_BOX, MMS_FP32);
+    if (zc <= 0) {
+        const int64_t cols = (int64_t)g.ntx * g.nty;
+        zc = (int)((int64_t)g.nz * cols / 4096);
+        zc = zc < 16 ? 16 : zc;
+    }
+    g.zchunk = zc;
+    g.nzc = (g.nz + zc - 1) / zc;
+    for (int i = 0; i < W * W * W; ++i) a.c[i] = coeffs[i];
+    const int64_t nblk = (int64_t)g.ntx * g.nty * g.nzc;
+    if (nblk > 0x7fffffff) return MMS_EINVAL;
+    hipLaunchKernelGGL((box_valu_kernel<R, TX, TY>), dim3((unsigned)nblk), dim3(TX * TY), 0, s, a);
+    return check_launch("box_valu_kernel");
+}
+
+}  // namespace
+
+int launch_box_valu(const float *in, float *out, const mms_grid *g, int r, const float *coeffs,
+                    hipStream_t s) {
+    switch (r) {
+        case 1: return launch_r<1>(in, out, g, coeffs, s);
+        case 2: return launch_r<2>(in, out, g, coeffs, s);
+        case 3: return launch_r<3>(in, out, g, coeffs, s);
+        case 4: return launch_r<4>(in, out, g, coeffs, s);
+        default: return MMS_EUNSUPPORTED;
+    }
+}
+
+}  // namespace mms

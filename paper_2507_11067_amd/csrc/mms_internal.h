@@ -1,0 +1,61 @@
+// Internal declarations shared by the HIP translation units of libmmstencil.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mmstencil.h"
+
+namespace mms {
+
+// Records a HIP error for mms_last_error() and returns MMS_EHIP.
+int hip_fail(hipError_t e, const char *where);
+// Checks hipGetLastError after a launch.
+int check_launch(const char *where);
+
+// Layout checks of the ABI (host side, before any HIP call).
+bool grid_ok(const mms_grid *g, int radius);
+inline int64_t grid_elems(const mms_grid *g) { return (g->nz + 2 * (int64_t)g->halo) * g->sz; }
+inline bool grid_empty(const mms_grid *g) { return g->nx == 0 || g->ny == 0 || g->nz == 0; }
+bool overlap(const void *a, int64_t abytes, const void *b, int64_t bbytes);
+
+// Launch geometry that every sweep kernel receives.
+struct Geom {
+    const float *in0;   // interior origin of the input
+    float *out0;        // interior origin of the output
+    int nx, ny, nz;
+    int H;
+    int64_t sy, sz;
+    int ntx, nty, nzc;  // tile counts along x, y and z chunks
+    int zchunk;
+};
+
+int zchunk_override(int shape, int precision);
+
+// Sweep launchers (host), one per kernel family.  coeffs is a host array.
+int launch_star(const float *in, float *out, const mms_grid *g, int r, const float *coeffs,
+                hipStream_t s);
+int launch_box_valu(const float *in, float *out, const mms_grid *g, int r, const float *coeffs,
+                    hipStream_t s);
+int launch_box_mfma(const float *in, float *out, const mms_grid *g, int r, const float *coeffs,
+                    int precision, hipStream_t s);
+
+}  // namespace mms
+
+// 16-byte load that yields zeros when `ok` is false.  The address is replaced by
+// `safe` (any valid 16-byte aligned address of the same buffer family) rather
+// than the value being selected after a conditional load, which keeps the load
+// a plain global load with no speculative path.
+__device__ __forceinline__ float4 guarded_load(const float *p, bool ok, const float *safe) {
+    const float4 v = *reinterpret_cast<const float4 *>(ok ? p : safe);
+    return ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of the MI355X (block b runs
+// on XCD b % 8).  This bijection gives every XCD one contiguous range of
+// logical tiles, so tiles that share halo cells share one L2.
+__device__ __forceinline__ int mms_xcd_remap(int b, int n) {
+    const int per = n >> 3, rem = n & 7;
+    const int xcd = b & 7, idx = b >> 3;
+    return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}

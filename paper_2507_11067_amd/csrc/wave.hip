@@ -1,0 +1,498 @@
+// Fused acoustic wave step, its adjoint, and the discrete energy (gfx950).
+//
+// Forward step (the leapfrog update RTM is built on, Sec. II-A), one launch per
+// time level:
+//   u^{n+1} = G (2 u^n - G u^{n-1} + C2 S(u^n)) + dt^2 f^n delta_src
+// with the receiver reading d^n = u^n(z = 0) and the FP64 image
+// I += (u^{n+1})^2 fused in.  Adjoint step (exact transpose of the recurrence):
+//   lam^n = 2 G lam^{n+1} - G^2 lam^{n+2} + S(C2 G lam^{n+1}) + R^T r^n
+//   grad += G lam^{n+1} S(u^n)                    (FP64)
+// S is the symmetric star, so S^T = S.  Both kernels stream z through an
+// (x, y) tile like the star sweep: the stencil operands travel through a
+// register queue of 2r+1 planes (z terms) and a double-buffered LDS plane
+// (x and y terms); the point-wise operands are requested one plane ahead.
+// The intermediate fields S(u^n), C2 G lam^{n+1} and S(C2 G lam^{n+1}) never
+// reach memory (the paper's thread-private intermediate buffers, Sec. IV-G).
+// The sponge factor is separable, G = gz(z) gy(y) gx(x); each lane evaluates
+// the x and y factors of its cells once and gz once per plane.
+#include "mms_internal.h"
+
+namespace mms {
+namespace {
+
+enum { MODE_FWD = 0, MODE_ADJ = 1, MODE_ENERGY = 2 };
+
+struct WaveArgs {
+    Geom g;
+    float c[9];           // per-axis weights, k + r (symmetric)
+    const float *f0;      // stencil field: u^n (FWD, ENERGY) or lam^{n+1} (ADJ)
+    const float *fu;      // ADJ: u^n (second stencil field, for the gradient)
+    const float *c2;      // c2 field (interior origin); C2 = c2s * c2
+    float c2s;
+    const float *p0;      // point-wise: u^{n-1} (FWD), lam^{n+2} (ADJ), u^{n+1} (ENERGY)
+    float *out;           // u^{n+1} (FWD), lam^n (ADJ)
+    float *traces;        // FWD: [ny][nx] plane of level n, or NULL
+    const float *resid;   // ADJ: [ny][nx] plane of level n, or NULL
+    double *acc64;        // FWD: image, ADJ: grad (dense [nz][ny][nx]), or NULL
+    double *partials;     // ENERGY: one FP64 partial per block
+    const float *src;     // device pointer to dt^2 f^n, or NULL
+    int src_z, src_y, src_x;
+    int sponge_w;
+    float sponge_a;
+    int faces;
+};
+
+__device__ __forceinline__ float g1(int d, int W, float a) {
+    if (d >= W) return 1.0f;
+    const float t = a * (float)(W - d);
+    return __expf(-t * t);
+}
+// damping factor of one axis at interior index i of n
+__device__ __forceinline__ float gaxis(int i, int n, int W, float a, bool lo, bool hi) {
+    float f = 1.0f;
+    if (lo) f *= g1(i, W, a);
+    if (hi) f *= g1(n - 1 - i, W, a);
+    return f;
+}
+
+template <int R, int MODE, bool GRAD, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
+    constexpr int NF = (MODE == MODE_ADJ && GRAD) ? 2 : 1;  // stencil fields
+    constexpr int Q = 2 * R + 1;
+    constexpr int BX = 4 * TX, BY = TY;
+    constexpr int LW4 = TX + 2, LH = BY + 2 * R;
+    constexpr int NT = TX * TY;
+    constexpr int NH = 2 * R * LW4 + 2 * BY;
+    constexpr int NHK = (NH + NT - 1) / NT;
+    __shared__ float4 tile[NF][2][LH][LW4];
+    __shared__ double sred[NT / 64];
+
+    const Geom &g = a.g;
+    int b = mms_xcd_remap(blockIdx.x, gridDim.x);
+    const int txi = b % g.ntx;
+    b /= g.ntx;
+    const int tyi = b % g.nty;
+    const int zci = b / g.nty;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int xt = txi * BX, yt = tyi * BY;
+    const int x0 = xt + 4 * tx, y = yt + ty;
+    const int zb = zci * g.zchunk;
+    const int ze = min(zb + g.zchunk, g.nz);
+    const int nx4 = (g.nx + 3) & ~3;
+    const int ylim = g.ny + g.H;
+    const int64_t sy = g.sy, sz = g.sz;
+    const int W = a.sponge_w;
+    const float sa = a.sponge_a;
+
+    const bool own_ok = (x0 <= nx4) && (y < ylim);
+    const int64_t own_off = (int64_t)y * sy + x0;
+    // sponge factors gy(y) gx(x) of the lane's own cells
+    float gown[4];
+    {
+        const float gy = gaxis(y, g.ny, W, sa, a.faces & 4, a.faces & 8);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) gown[e] = gy * gaxis(x0 + e, g.nx, W, sa, a.faces & 1, a.faces & 2);
+    }
+    int64_t h_off[NHK];
+    int h_lds[NHK];
+    bool h_ok[NHK];
+    float hg[NHK][4];  // ADJ: gy gx of the halo cells (C2 G lam is formed on load)
+#pragma unroll
+    for (int k = 0; k < NHK; ++k) {
+        const int i = tid + k * NT;
+        int row, lrow, col4, x;
+        if (i < 2 * R * LW4) {
+            const int hr = i / LW4, hc = i % LW4;
+            row = hr < R ? yt - R + hr : yt + BY + (hr - R);
+            lrow = hr < R ? hr : hr + BY;
+            col4 = hc;
+            x = xt - 4 + 4 * hc;
+        } else {
+            const int j = i - 2 * R * LW4;
+            row = yt + j / 2;
+            lrow = R + j / 2;
+            col4 = (j & 1) ? LW4 - 1 : 0;
+            x = (j & 1) ? xt + BX : xt - 4;
+        }
+        h_ok[k] = (i < NH) && (row < ylim) && (x <= nx4);
+        h_off[k] = (int64_t)row * sy + x;
+        h_lds[k] = lrow * LW4 + col4;
+        if constexpr (MODE == MODE_ADJ) {
+            const float gy = gaxis(row, g.ny, W, sa, a.faces & 4, a.faces & 8);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                hg[k][e] = gy * gaxis(x + e, g.nx, W, sa, a.faces & 1, a.faces & 2);
+        }
+    }
+    (void)hg;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    const bool zlo = a.faces & 16, zhi = a.faces & 32;
+
+    auto ld = [&](const float *base, int z, int64_t off, bool ok) -> float4 {
+        return guarded_load(base + (int64_t)z * sz + off, ok, a.c2);
+    };
+    auto mul4 = [](float4 v, const float *s, float t) {
+        return make_float4(v.x * s[0] * t, v.y * s[1] * t, v.z * s[2] * t, v.w * s[3] * t);
+    };
+    // stencil field f of plane z at the lane's own cells / halo item k
+    auto own_field = [&](int f, int z) -> float4 {
+        if (MODE == MODE_ADJ && f == 0) {
+            const float4 l = ld(a.f0, z, own_off, own_ok);
+            const float4 c = ld(a.c2, z, own_off, own_ok);
+            const float gz = a.c2s * gaxis(z, g.nz, W, sa, zlo, zhi);
+            return mul4(make_float4(l.x * c.x, l.y * c.y, l.z * c.z, l.w * c.w), gown, gz);
+        }
+        return ld(f == 0 ? a.f0 : a.fu, z, own_off, own_ok);
+    };
+    auto halo_field = [&](int f, int z, int k) -> float4 {
+        if (MODE == MODE_ADJ && f == 0) {
+            const float4 l = ld(a.f0, z, h_off[k], h_ok[k]);
+            const float4 c = ld(a.c2, z, h_off[k], h_ok[k]);
+            const float gz = a.c2s * gaxis(z, g.nz, W, sa, zlo, zhi);
+            return mul4(make_float4(l.x * c.x, l.y * c.y, l.z * c.z, l.w * c.w), hg[k], gz);
+        }
+        return ld(f == 0 ? a.f0 : a.fu, z, h_off[k], h_ok[k]);
+    };
+    auto lds_store = [&](int buf, float4 (*own)[Q], int slot, float4 (*halo)[NHK]) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            float4 *t = &tile[f][buf][0][0];
+            t[(R + ty) * LW4 + tx + 1] = own[f][slot];
+#pragma unroll
+            for (int k = 0; k < NHK; ++k)
+                if (tid + k * NT < NH) t[h_lds[k]] = halo[f][k];
+        }
+    };
+
+    float4 q[NF][Q];
+    float4 hreg[NF][NHK];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) q[f][i] = own_field(f, zb - R + i);
+#pragma unroll
+        for (int k = 0; k < NHK; ++k) hreg[f][k] = halo_field(f, zb, k);
+    }
+    lds_store(0, q, R, hreg);
+    // point-wise operands of the first plane
+    float4 pw0 = ld(a.p0, zb, own_off, own_ok);
+    float4 pw1 = (MODE == MODE_ADJ) ? ld(a.f0, zb, own_off, own_ok) : ld(a.c2, zb, own_off, own_ok);
+    __syncthreads();
+
+    const float *c = a.c;
+    const float srcv = (MODE == MODE_FWD && a.src) ? *a.src : 0.f;
+    double esum = 0.0;
+    int buf = 0;
+    for (int z = zb; z < ze;) {
+#pragma unroll
+        for (int ph = 0; ph < Q; ++ph) {
+            if (z < ze) {
+                const bool more = z + 1 < ze;
+                float4 nq[NF];
+                float4 npw0 = zero4, npw1 = zero4;
+                if (more) {
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) {
+                        nq[f] = own_field(f, z + R + 1);
+#pragma unroll
+                        for (int k = 0; k < NHK; ++k) hreg[f][k] = halo_field(f, z + 1, k);
+                    }
+                    npw0 = ld(a.p0, z + 1, own_off, own_ok);
+                    npw1 = (MODE == MODE_ADJ) ? ld(a.f0, z + 1, own_off, own_ok)
+                                              : ld(a.c2, z + 1, own_off, own_ok);
+                }
+                float o[NF][4];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const float4 *t = &tile[f][buf][0][0];
+                    const float4 ctr = q[f][(ph + R) % Q];
+                    float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int k = -R; k <= R; ++k) {
+                        const float4 vz = q[f][(ph + R + k + Q) % Q];
+                        const float4 vy = k == 0 ? ctr : t[(R + ty + k) * LW4 + tx + 1];
+                        const float ck = c[R + k];
+                        s[0] = fmaf(ck, vz.x + vy.x, s[0]);
+                        s[1] = fmaf(ck, vz.y + vy.y, s[1]);
+                        s[2] = fmaf(ck, vz.z + vy.z, s[2]);
+                        s[3] = fmaf(ck, vz.w + vy.w, s[3]);
+                    }
+                    const float4 L = t[(R + ty) * LW4 + tx];
+                    const float4 Rr = t[(R + ty) * LW4 + tx + 2];
+                    const float w[12] = {L.x,   L.y,   L.z,   L.w,  ctr.x, ctr.y,
+                                         ctr.z, ctr.w, Rr.x, Rr.y, Rr.z,  Rr.w};
+#pragma unroll
+                    for (int k = -R; k <= R; ++k)
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) s[e] = fmaf(c[R + k], w[4 + e + k], s[e]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) o[f][e] = s[e];
+                }
+                const float gz = gaxis(z, g.nz, W, sa, zlo, zhi);
+                const bool live = y < g.ny && x0 < g.nx;
+                const int64_t dense = ((int64_t)z * g.ny + y) * g.nx + x0;
+                float *po = a.out ? a.out + (int64_t)z * sz + own_off : nullptr;
+                const float p0v[4] = {pw0.x, pw0.y, pw0.z, pw0.w};
+                const float p1v[4] = {pw1.x, pw1.y, pw1.z, pw1.w};
+                const float4 ctr0 = q[0][(ph + R) % Q];
+                const float cv[4] = {ctr0.x, ctr0.y, ctr0.z, ctr0.w};
+                float r[4];
+                if constexpr (MODE == MODE_FWD) {
+                    // p0 = u^{n-1}, p1 = C2, ctr = u^n
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float G = gz * gown[e];
+                        r[e] = G * (2.0f * cv[e] - G * p0v[e] + a.c2s * p1v[e] * o[0][e]);
+                    }
+                    if (srcv != 0.f && z == a.src_z && y == a.src_y && a.src_x >= x0 &&
+                        a.src_x < x0 + 4) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (x0 + e == a.src_x) r[e] += srcv;
+                    }
+                } else if constexpr (MODE == MODE_ADJ) {
+                    // p0 = lam^{n+2}, p1 = lam^{n+1}
+                    const float *rs = (a.resid && z == 0) ? a.resid + (int64_t)y * g.nx + x0 : nullptr;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float G = gz * gown[e];
+                        r[e] = 2.0f * G * p1v[e] - G * G * p0v[e] + o[0][e];
+                        if (rs && live && x0 + e < g.nx) r[e] += rs[e];
+                    }
+                } else {
+                    // ENERGY: p0 = u^{n+1}, p1 = C2, ctr = u^n, o = S u^n
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if (live && x0 + e < g.nx) {
+                            const double d = (double)p0v[e] - (double)cv[e];
+                            double t = -(double)p0v[e] * (double)o[0][e];
+                            if (p1v[e] != 0.f) t += d * d / ((double)a.c2s * (double)p1v[e]);
+                            esum += t;
+                        }
+                    }
+                }
+                if (MODE != MODE_ENERGY && live) {
+                    if (x0 + 3 < g.nx) {
+                        *reinterpret_cast<float4 *>(po) = make_float4(r[0], r[1], r[2], r[3]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (x0 + e < g.nx) po[e] = r[e];
+                    }
+                    if (MODE == MODE_FWD && a.traces && z == 0) {
+                        float *pt = a.traces + (int64_t)y * g.nx + x0;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (x0 + e < g.nx) pt[e] = cv[e];
+                    }
+                    if (a.acc64) {
+                        double *pa = a.acc64 + dense;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            if (x0 + e < g.nx) {
+                                if constexpr (MODE == MODE_FWD) {
+                                    pa[e] += (double)r[e] * (double)r[e];
+                                } else if constexpr (GRAD) {
+                                    pa[e] += (double)(a.c2s * gz * gown[e] * p1v[e] * o[NF - 1][e]);
+                                }
+                            }
+                        }
+                    }
+                }
+                if (more) {
+                    lds_store(buf ^ 1, q, (ph + R + 1) % Q, hreg);
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) q[f][ph] = nq[f];
+                    pw0 = npw0;
+                    pw1 = npw1;
+                }
+                __syncthreads();
+                buf ^= 1;
+                ++z;
+            }
+        }
+    }
+    if constexpr (MODE == MODE_ENERGY) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) esum += __shfl_xor(esum, o);
+        if ((tid & 63) == 0) sred[tid >> 6] = esum;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < NT / 64; ++w) s += sred[w];
+            a.partials[blockIdx.x] = s;
+        }
+    }
+}
+
+// lam^0 = -G^2 lam^2 + R^T r^0 (point-wise; u^0 enters only through step 1's G^2 term)
+__global__ void adjoint_first_kernel(WaveArgs a) {
+    const Geom &g = a.g;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t np = (int64_t)g.nx * g.ny * g.nz;
+    if (i >= np) return;
+    const int x = (int)(i % g.nx);
+    const int y = (int)((i / g.nx) % g.ny);
+    const int z = (int)(i / ((int64_t)g.nx * g.ny));
+    const int64_t off = (int64_t)z * g.sz + (int64_t)y * g.sy + x;
+    const int W = a.sponge_w;
+    const float G = gaxis(z, g.nz, W, a.sponge_a, a.faces & 16, a.faces & 32) *
+                    gaxis(y, g.ny, W, a.sponge_a, a.faces & 4, a.faces & 8) *
+                    gaxis(x, g.nx, W, a.sponge_a, a.faces & 1, a.faces & 2);
+    float v = -G * G * a.p0[off];
+    if (a.resid && z == 0) v += a.resid[(int64_t)y * g.nx + x];
+    a.out[off] = v;
+}
+
+__global__ void dense_to_grid_kernel(const double *in, float *out, int nx, int ny, int64_t sy,
+                                     int64_t sz, double scale) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x < nx) out[(int64_t)z * sz + (int64_t)y * sy + x] =
+        (float)(scale * in[((int64_t)z * ny + y) * nx + x]);
+}
+
+__global__ void record_kernel(const float *u0, float *tr, int nx, int ny, int64_t sy) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x < nx) tr[(int64_t)y * nx + x] = u0[(int64_t)y * sy + x];
+}
+
+__global__ void sum_partials_kernel(const double *p, int n, double *out) {
+    __shared__ double s[256];
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) v += p[i];
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+constexpr int WTX = 32, WTY = 8;
+
+void fill_geom(Geom &g, const mms_grid *gd, int zdiv) {
+    g.H = gd->halo;
+    g.nx = (int)gd->nx;
+    g.ny = (int)gd->ny;
+    g.nz = (int)gd->nz;
+    g.sy = gd->sy;
+    g.sz = gd->sz;
+    g.ntx = (g.nx + 4 * WTX - 1) / (4 * WTX);
+    g.nty = (g.ny + WTY - 1) / WTY;
+    const int64_t cols = (int64_t)g.ntx * g.nty;
+    int zc = (int)((int64_t)g.nz * cols / zdiv);
+    g.zchunk = zc < 16 ? 16 : zc;
+    g.nzc = (g.nz + g.zchunk - 1) / g.zchunk;
+}
+
+WaveArgs base_args(const mms_wave *w) {
+    WaveArgs a{};
+    fill_geom(a.g, &w->g, 2048);
+    const int r = w->radius;
+    for (int k = -r; k <= r; ++k) a.c[k + r] = w->lap[k < 0 ? -k : k];
+    a.sponge_w = w->sponge_width;
+    a.sponge_a = w->sponge_alpha;
+    a.faces = w->sponge_faces;
+    const int64_t o = (int64_t)w->g.halo * (w->g.sz + w->g.sy + 1);
+    a.c2 = w->c2 + o;
+    a.c2s = w->c2_scale;
+    return a;
+}
+
+template <int MODE, bool GRAD>
+int launch_mode(const WaveArgs &a, int r, hipStream_t s) {
+    const int64_t nblk = (int64_t)a.g.ntx * a.g.nty * a.g.nzc;
+    if (nblk > 0x7fffffff) return MMS_EINVAL;
+    const dim3 grid((unsigned)nblk), block(WTX * WTY);
+    switch (r) {
+        case 1: hipLaunchKernelGGL((wave_kernel<1, MODE, GRAD, WTX, WTY>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((wave_kernel<2, MODE, GRAD, WTX, WTY>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((wave_kernel<3, MODE, GRAD, WTX, WTY>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((wave_kernel<4, MODE, GRAD, WTX, WTY>), grid, block, 0, s, a); break;
+        default: return MMS_EUNSUPPORTED;
+    }
+    return check_launch("wave_kernel");
+}
+
+}  // namespace
+
+int wave_step(const mms_wave *w, int n, const float *up, const float *uc, float *un, hipStream_t s) {
+    WaveArgs a = base_args(w);
+    const int64_t o = (int64_t)w->g.halo * (w->g.sz + w->g.sy + 1);
+    a.f0 = uc + o;
+    a.p0 = up + o;
+    a.out = un + o;
+    a.traces = w->traces ? w->traces + (int64_t)n * w->g.ny * w->g.nx : nullptr;
+    a.acc64 = w->image;
+    a.src = (w->src_dt2f && n >= 0 && n < w->nt) ? w->src_dt2f + n : nullptr;
+    a.src_z = (int)w->src_z;
+    a.src_y = (int)w->src_y;
+    a.src_x = (int)w->src_x;
+    return launch_mode<MODE_FWD, false>(a, w->radius, s);
+}
+
+int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1, float *l0,
+                      const float *resid, const float *un, double *grad, hipStream_t s) {
+    WaveArgs a = base_args(w);
+    const int64_t o = (int64_t)w->g.halo * (w->g.sz + w->g.sy + 1);
+    a.p0 = l2 + o;
+    a.out = l0 + o;
+    a.resid = resid ? resid + (int64_t)n * w->g.ny * w->g.nx : nullptr;
+    if (n == 0) {
+        const int64_t np = w->g.nx * w->g.ny * w->g.nz;
+        const unsigned nb = (unsigned)((np + 255) / 256);
+        hipLaunchKernelGGL(adjoint_first_kernel, dim3(nb), dim3(256), 0, s, a);
+        return check_launch("adjoint_first_kernel");
+    }
+    a.f0 = l1 + o;
+    if (grad) {
+        a.fu = un + o;
+        a.acc64 = grad;
+        return launch_mode<MODE_ADJ, true>(a, w->radius, s);
+    }
+    return launch_mode<MODE_ADJ, false>(a, w->radius, s);
+}
+
+int wave_record(const mms_wave *w, int n, const float *u, hipStream_t s) {
+    const int64_t o = (int64_t)w->g.halo * (w->g.sz + w->g.sy + 1);
+    const dim3 grid((unsigned)((w->g.nx + 255) / 256), (unsigned)w->g.ny);
+    hipLaunchKernelGGL(record_kernel, grid, dim3(256), 0, s, u + o,
+                       w->traces + (int64_t)n * w->g.ny * w->g.nx, (int)w->g.nx, (int)w->g.ny,
+                       w->g.sy);
+    return check_launch("record_kernel");
+}
+
+int dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, hipStream_t s) {
+    const int64_t o = (int64_t)g->halo * (g->sz + g->sy + 1);
+    const dim3 grid((unsigned)((g->nx + 255) / 256), (unsigned)g->ny, (unsigned)g->nz);
+    hipLaunchKernelGGL(dense_to_grid_kernel, grid, dim3(256), 0, s, in, out + o, (int)g->nx,
+                       (int)g->ny, g->sy, g->sz, scale);
+    return check_launch("dense_to_grid_kernel");
+}
+
+int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *out, double *partials,
+                int64_t npartials, hipStream_t s) {
+    WaveArgs a = base_args(w);
+    const int64_t o = (int64_t)w->g.halo * (w->g.sz + w->g.sy + 1);
+    a.f0 = un + o;
+    a.p0 = unp1 + o;
+    a.partials = partials;
+    const int64_t nblk = (int64_t)a.g.ntx * a.g.nty * a.g.nzc;
+    if (nblk > npartials) return MMS_ENOMEM;
+    int rc = launch_mode<MODE_ENERGY, false>(a, w->radius, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partials, (int)nblk, out);
+    return check_launch("sum_partials_kernel");
+}
+
+int64_t wave_energy_blocks(const mms_wave *w) {
+    WaveArgs a = base_args(w);
+    return (int64_t)a.g.ntx * a.g.nty * a.g.nzc;
+}
+
+}  // namespace mms

@@ -1,0 +1,112 @@
+"""The C ABI loads, exports every declared entry point and rejects bad arguments
+on the host, before any HIP call (these tests need no GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mmstencil.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2507_11067_amd import _lib
+    return _lib.lib()
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(mms_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported(L):
+    names = declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2507_11067_amd import _lib
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_version_and_strerror(L):
+    assert L.mms_abi_version() == 1
+    for code in (0, -1, -2, -3, -4):
+        assert L.mms_strerror(code)
+
+
+def grid(nx=16, ny=16, nz=16, H=4, sy=None, sz=None):
+    from paper_2507_11067_amd._lib import MmsGrid
+    sy = ((nx + 3) // 4) * 4 + 2 * H if sy is None else sy
+    sz = sy * (ny + 2 * H) if sz is None else sz
+    return MmsGrid(nx, ny, nz, H, 0, sy, sz)
+
+
+FAKE_IN = ctypes.c_void_p(0x10000)    # never dereferenced: every case fails validation
+FAKE_OUT = ctypes.c_void_p(0x4000000)
+
+
+def apply(L, g, shape=0, r=4, ncoeffs=None, prec=0, inp=FAKE_IN, out=FAKE_OUT, coeffs=True):
+    n = ncoeffs if ncoeffs is not None else (3 * (2 * r + 1) if shape == 0 else (2 * r + 1) ** 3)
+    buf = (ctypes.c_float * max(n, 1))()
+    c = ctypes.cast(buf, ctypes.POINTER(ctypes.c_float)) if coeffs else None
+    return L.mms_stencil_apply(inp, out, ctypes.byref(g) if g is not None else None, shape, r,
+                               c, n, prec, None)
+
+
+def test_stencil_apply_validation(L):
+    EINVAL, EUNS = -1, -2
+    assert apply(L, grid(), r=0) == EUNS
+    assert apply(L, grid(), r=5) == EUNS
+    assert apply(L, grid(), shape=2) == EUNS
+    assert apply(L, grid(), shape=0, prec=1) == EUNS        # split precision on a star
+    assert apply(L, grid(), prec=7) == EUNS
+    assert apply(L, None) == EINVAL
+    assert apply(L, grid(), inp=None) == EINVAL
+    assert apply(L, grid(), coeffs=False) == EINVAL
+    assert apply(L, grid(), ncoeffs=26) == EINVAL
+    assert apply(L, grid(), shape=1, ncoeffs=728) == EINVAL
+    assert apply(L, grid(H=2), r=4) == EINVAL               # halo < radius
+    assert apply(L, grid(H=6), r=4) == EINVAL               # halo not a multiple of 4
+    assert apply(L, grid(sy=22)) == EINVAL                  # pitch not a multiple of 4
+    assert apply(L, grid(sy=20)) == EINVAL                  # pitch too small
+    assert apply(L, grid(sz=24 * 23)) == EINVAL             # plane stride too small
+    assert apply(L, grid(nx=-1)) == EINVAL
+    assert apply(L, grid(), out=ctypes.c_void_p(0x10008)) == EINVAL  # misaligned / overlapping
+    assert apply(L, grid(), out=ctypes.c_void_p(0x10010)) == EINVAL  # overlapping
+
+
+def test_wave_validation(L):
+    from paper_2507_11067_amd._lib import MmsWave
+    lap = (ctypes.c_float * 5)(-2.8, 1.6, -0.2, 0.025, -0.0018)
+    w = MmsWave(grid(), 4, lap, ctypes.c_void_p(0x20000), 1.0, 8, 0.015, 47, 10, 2, 3, 4,
+                None, None, None)
+    vp = ctypes.c_void_p
+    a, b, c = vp(0x100000), vp(0x800000), vp(0x1000000)
+    assert L.mms_wave_step(ctypes.byref(w), 0, a, b, c, None) == -1      # n out of range
+    assert L.mms_wave_step(ctypes.byref(w), 10, a, b, c, None) == -1
+    assert L.mms_wave_step(ctypes.byref(w), 1, a, b, b, None) == -1      # u_next aliases u_cur
+    assert L.mms_wave_step(ctypes.byref(w), 1, None, b, c, None) == -1
+    assert L.mms_wave_record(ctypes.byref(w), 0, a, None) == -1          # no trace buffer
+    w.radius = 5
+    assert L.mms_wave_step(ctypes.byref(w), 1, a, b, c, None) == -2
+    w.radius = 4
+    w.src_dt2f = vp(0x30000)
+    w.src_z = 99                                                          # source off the grid
+    assert L.mms_wave_step(ctypes.byref(w), 1, a, b, c, None) == -1
+    w.src_z = 2
+    assert L.mms_wave_adjoint_step(ctypes.byref(w), 3, a, b, b, None, None, None, None) == -1
+    assert L.mms_wave_adjoint_step(ctypes.byref(w), 3, a, b, c, None, None, vp(0x40), None) == -1
+    arr = (vp * 3)(a, b, c)
+    assert L.mms_wave_forward(ctypes.byref(w), 0, 3, arr, None) == -1
+    assert L.mms_wave_forward(ctypes.byref(w), 1, 11, arr, None) == -1
+
+
+def test_python_binding_requires_library(monkeypatch, tmp_path):
+    """The binding raises instead of computing anything on the CPU when the library is absent."""
+    from paper_2507_11067_amd import _lib
+    monkeypatch.setattr(_lib, "LIB", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.lib()

@@ -1,0 +1,263 @@
+"""GPU parity of the fused wave step, its adjoint, the energy and the reductions
+against the FP64 oracle, plus the adjoint identities on the GPU.
+
+Gates: one step from identical FP32 inputs, normwise max error <= 1e-5;
+multi-step runs accumulate FP32 rounding and are gated at 1e-3 (numbers are
+printed); the dot-product identity is gated at 1e-5 relative.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.helpers import interior, rel_errors
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+LAP = [float(v) for v in synth.LAPLACIAN_R4]
+
+
+@pytest.fixture(scope="module")
+def mms():
+    import paper_2507_11067_amd as m
+    return m
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def setup_small(mms, n, nt, seed, W=4, ny=None, nz=None):
+    ny = n if ny is None else ny
+    nz = n if nz is None else nz
+    grid = mms.Grid(n, ny, nz)
+    v = synth.layered_velocity(n, seed, nz=nz, ny=ny, sigma=2.0)
+    dt = 0.4 * 10.0 / v.max()
+    c2 = synth.padded_zeros(n, ny, nz, sy=grid.sy)
+    synth.interior(c2, n, ny, nz)[...] = ((v * dt / 10.0) ** 2).astype(np.float32)
+    f = (dt * dt * synth.ricker(nt, dt, 15.0) * 1e4).astype(np.float32)
+    src = (min(2, nz - 1), ny // 2, n // 2)
+    return grid, c2, f, src, dt
+
+
+def oracle_wave(grid, c2, f, src, nt, W, faces=synth.SPONGE_LATERAL_AND_BOTTOM, alpha=0.1):
+    return oracle.Wave(grid.nx, grid.ny, grid.nz, c2, LAP, src, f, nt, W, alpha, faces)
+
+
+def gpu_wave(mms, grid, c2t, ft, src, nt, W, faces=synth.SPONGE_LATERAL_AND_BOTTOM, alpha=0.1,
+             traces=None, image=None):
+    return mms.Wave(grid, c2t, LAP, nt, 1.0, W, alpha, faces, src, ft, traces, image)
+
+
+def smooth(seed, grid):
+    return synth.smooth_random_grid(seed, grid.nx, grid.ny, grid.nz)
+
+
+@pytest.mark.parametrize("dims", [(20, 20, 20), (37, 19, 11), (128, 8, 16)],
+                         ids=lambda d: "x".join(map(str, d)))
+def test_forward_step_parity(mms, dims):
+    nx, ny, nz = dims
+    nt, n = 10, 5
+    grid, c2, f, src, _ = setup_small(mms, nx, nt, 1, ny=ny, nz=nz)
+    up, uc = smooth(2, grid), smooth(3, grid)
+    traces = torch.zeros((nt, ny, nx), device=DEV)
+    image = torch.zeros((nz, ny, nx), dtype=torch.float64, device=DEV)
+    w = gpu_wave(mms, grid, T(c2), T(f), src, nt, 4, traces=traces, image=image)
+    un = grid.zeros(DEV)
+    w.step(n, T(up), T(uc), un)
+    # in place: u_next = u_prev gives the same bits
+    upt = T(up)
+    w2 = gpu_wave(mms, grid, T(c2), T(f), src, nt, 4)
+    w2.step(n, upt, T(uc), upt)
+    torch.cuda.synchronize()
+    ow = oracle_wave(grid, c2, f, src, nt, 4)
+    img = ow.zeros()
+    ref, tr = ow.step(n, up, uc, image=img)
+    got = un.cpu().numpy()
+    rmax, rrms = rel_errors(interior(got, grid), interior(ref, grid))
+    assert rmax <= 1e-5, (rmax, rrms)
+    assert torch.equal(upt, un)
+    np.testing.assert_array_equal(traces[n].cpu().numpy(), tr.astype(np.float32))
+    assert torch.count_nonzero(traces[:n]) == 0 and torch.count_nonzero(traces[n + 1:]) == 0
+    ri, _ = rel_errors(image.cpu().numpy(), interior(img, grid))
+    assert ri <= 1e-5
+    # the source cell received dt^2 f^n
+    assert abs(got[src[0] + 4, src[1] + 4, src[2] + 4]) > 0
+
+
+@pytest.mark.parametrize("n_step", [0, 1, 6])
+def test_adjoint_step_parity(mms, n_step):
+    nx, ny, nz = 30, 22, 18
+    nt = 10
+    grid, c2, f, src, _ = setup_small(mms, nx, nt, 4, ny=ny, nz=nz)
+    l2, l1, un = smooth(5, grid), smooth(6, grid), smooth(7, grid)
+    resid = np.random.default_rng(8).standard_normal((nt, ny, nx)).astype(np.float32)
+    w = gpu_wave(mms, grid, T(c2), T(f), src, nt, 4)
+    grad = torch.full((nz, ny, nx), 0.25, dtype=torch.float64, device=DEV)
+    l0 = grid.zeros(DEV)
+    w.adjoint_step(n_step, T(l2), T(l1), l0, resid=T(resid), u_n=T(un), grad=grad)
+    torch.cuda.synchronize()
+    ow = oracle_wave(grid, c2, f, src, nt, 4)
+    g = ow.zeros()
+    synth.interior(g, nx, ny, nz)[...] = 0.25
+    ref = ow.adjoint_step(n_step, l2, l1, resid[n_step], un if n_step >= 1 else None, g)
+    rmax, rrms = rel_errors(interior(l0.cpu().numpy(), grid), interior(ref, grid))
+    assert rmax <= 1e-5, (rmax, rrms)
+    gg = grad.cpu().numpy() - 0.25
+    gr = interior(g, grid) - 0.25
+    if n_step == 0:
+        assert np.all(gg == 0)
+    else:
+        rg, _ = rel_errors(gg, gr)
+        assert rg <= 1e-5, rg
+
+
+def test_energy_matches_definition(mms):
+    n = 26
+    grid, c2, f, src, _ = setup_small(mms, n, 4, 9)
+    u0, u1 = smooth(10, grid), smooth(11, grid)
+    w = gpu_wave(mms, grid, T(c2), None, src, 4, 0, faces=0)
+    e = w.energy(T(u0), T(u1))
+    lapc = np.array([LAP[abs(k)] for k in range(-4, 5)])
+    Su = oracle.star(u0, n, n, n, 4, np.stack([lapc] * 3))
+    I = lambda a: synth.interior(np.asarray(a, dtype=np.float64), n, n, n)
+    ref = np.sum((I(u1) - I(u0)) ** 2 / I(c2)) - np.sum(I(u1) * I(Su))
+    assert abs(e - ref) <= 1e-6 * abs(ref)
+
+
+def test_reductions(mms):
+    n = 33
+    grid = mms.Grid(n, n - 2, n - 5)
+    a, b = smooth(12, grid), smooth(13, grid)
+    d = mms.dot(T(a), T(b), grid)
+    I = lambda x: interior(x.astype(np.float64), grid)
+    assert d == pytest.approx(np.sum(I(a) * I(b)), rel=1e-12, abs=1e-12)
+    assert mms.dot(T(a), None, grid) == pytest.approx(np.sum(I(a) ** 2), rel=1e-12)
+    x = np.random.default_rng(1).standard_normal(100003).astype(np.float32)
+    y = np.random.default_rng(2).standard_normal(100003).astype(np.float32)
+    assert mms.flat_dot(T(x), T(y)) == pytest.approx(np.dot(x.astype(np.float64), y), rel=1e-12)
+    r = torch.empty(100003, device=DEV)
+    J = mms.flat_misfit(T(x), T(y), resid=r).item()
+    ref = 0.5 * np.sum((x - y).astype(np.float64) ** 2)
+    assert J == pytest.approx(ref, rel=1e-12)
+    np.testing.assert_array_equal(r.cpu().numpy(), x - y)
+    # bit-reproducible
+    assert mms.flat_dot(T(x), T(y)) == mms.flat_dot(T(x), T(y))
+
+
+def test_forward_run_vs_oracle(mms):
+    """Workload recipe at 48^3 (W = 8 sponge, Ricker source), 300 steps: traces vs FP64."""
+    n, nt = 48, 300
+    s = synth.wave_setup(n, nt, seed=21, sponge_width=8)
+    grid = mms.Grid(n, n, n)
+    traces = torch.zeros((nt, n, n), device=DEV)
+    image = torch.zeros((n, n, n), dtype=torch.float64, device=DEV)
+    w = mms.Wave(grid, T(s.c2), LAP, nt, 1.0, s.sponge_width, s.sponge_alpha, s.sponge_faces,
+                 s.src, T(s.src_dt2f), traces, image)
+    bufs = [grid.zeros(DEV) for _ in range(3)]
+    w.record(0, bufs[0])
+    w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+    torch.cuda.synchronize()
+    ow = oracle.Wave.from_setup(s, LAP)
+    z = ow.zeros()
+    res = ow.forward(z, z, image=True)
+    rmax, rrms = rel_errors(traces.cpu().numpy(), res["traces"])
+    ri, _ = rel_errors(image.cpu().numpy(), interior(res["image"], grid))
+    print(f"48^3 x {nt} forward: traces rel_max {rmax:.2e} rel_rms {rrms:.2e}; image {ri:.2e}")
+    assert rmax <= 1e-3 and ri <= 1e-3
+
+
+def test_energy_conserved_on_gpu(mms):
+    n, nt = 40, 400
+    grid, c2, f, src, _ = setup_small(mms, n, nt, 14)
+    w = gpu_wave(mms, grid, T(c2), None, src, nt, 0, faces=0)
+    bufs = [T(smooth(15, grid)), T(smooth(16, grid)), grid.zeros(DEV)]
+    e0 = w.energy(bufs[0], bufs[1])
+    w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+    e1 = w.energy(bufs[(nt - 1) % 3], bufs[nt % 3])
+    drift = abs(e1 - e0) / abs(e0)
+    print(f"energy drift over {nt} FP32 steps: {drift:.2e}")
+    assert drift <= 1e-4
+
+
+def dot_test(mms, n, nt, seed, W):
+    grid, c2, f, src, _ = setup_small(mms, n, nt, seed, W=W)
+    traces = torch.zeros((nt, n, n), device=DEV)
+    w = gpu_wave(mms, grid, T(c2), None, src, nt, W, traces=traces)
+    u0, u1 = T(smooth(seed + 1, grid)), T(smooth(seed + 2, grid))
+    bufs = [u0.clone(), u1.clone(), grid.zeros(DEV)]
+    w.record(0, bufs[0])
+    w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+    from scipy.ndimage import gaussian_filter
+    yn = gaussian_filter(np.random.default_rng(seed + 3).standard_normal((nt, n, n)), sigma=2.0)
+    y = torch.from_numpy((yn / np.abs(yn).max()).astype(np.float32)).to(DEV)
+    lam = [grid.zeros(DEV) for _ in range(3)]
+    w.adjoint(nt - 1, 0, [lam[i % 3] for i in range(nt + 2)], resid=y)
+    lhs = mms.flat_dot(traces, y)
+    rhs = mms.dot(u0, lam[0], grid) + mms.dot(u1, lam[1], grid)
+    return lhs, rhs
+
+
+def test_dot_product_identity_gpu(mms):
+    lhs, rhs = dot_test(mms, 64, 400, 30, 8)
+    rel = abs(lhs - rhs) / abs(lhs)
+    print(f"dot test 64^3 x 400: <Ax,y> = {lhs:.12e}, <x,A^T y> = {rhs:.12e}, rel {rel:.2e}")
+    assert rel <= 1e-5
+
+
+def autograd_problem(mms, n, nt, seed, K, W=8):
+    from paper_2507_11067_amd.autograd import Problem
+    s = synth.wave_setup(n, nt, seed=seed, sponge_width=W)
+    grid = mms.Grid(n, n, n)
+    m = synth.padded_zeros(n, n, n)
+    synth.interior(m, n, n, n)[...] = (s.v ** 2).astype(np.float32)
+    prob = Problem(grid, tuple(LAP), nt, s.h, s.dt, s.src, T(s.src_dt2f), s.sponge_width,
+                   s.sponge_alpha, s.sponge_faces, checkpoint_every=K)
+    return s, grid, m, prob
+
+
+def test_checkpointing_gives_identical_gradient(mms):
+    from paper_2507_11067_amd.autograd import misfit, propagate
+    n, nt = 32, 120
+    s, grid, m, prob = autograd_problem(mms, n, nt, 40, K=50)
+    d_obs = torch.zeros((nt, n, n), device=DEV)
+    grads = []
+    for K in (50, 7, 1000):
+        prob.checkpoint_every = K
+        mt = T(m).requires_grad_(True)
+        z0 = grid.zeros(DEV).requires_grad_(True)
+        z1 = grid.zeros(DEV).requires_grad_(True)
+        J = misfit(propagate(mt, z0, z1, prob), d_obs)
+        J.backward()
+        grads.append((mt.grad.clone(), z0.grad.clone(), z1.grad.clone()))
+    for gk in grads[1:]:
+        for a, b in zip(grads[0], gk):
+            assert torch.equal(a, b)
+    assert torch.count_nonzero(grads[0][0]) > 0
+
+
+def test_gradient_vs_oracle_64(mms):
+    """Gradient of the receiver misfit w.r.t. v^2 at 64^3 against the FP64 oracle."""
+    from paper_2507_11067_amd.autograd import misfit, propagate
+    n, nt = 64, 300
+    s, grid, m, prob = autograd_problem(mms, n, nt, 41, K=50)
+    s0 = synth.wave_setup(n, nt, seed=None, sponge_width=8, dt=s.dt)   # layers only
+    ow0 = oracle.Wave.from_setup(s0, LAP)
+    z = ow0.zeros()
+    d_obs = ow0.forward(z, z)["traces"]
+    mt = T(m).requires_grad_(True)
+    z0 = grid.zeros(DEV)
+    J = misfit(propagate(mt, z0, z0.clone(), prob), T(d_obs))
+    J.backward()
+    ow = oracle.Wave.from_setup(s, LAP)
+    res = ow.forward(z, z, keep_states=True)
+    g_c2, _, _, _ = ow.adjoint(res["states"], res["traces"] - d_obs)
+    g_ref = interior(g_c2, grid) * (s.dt / s.h) ** 2
+    got = interior(mt.grad.cpu().numpy(), grid)
+    rmax, rrms = rel_errors(got, g_ref)
+    J_ref = 0.5 * np.sum((res["traces"] - d_obs) ** 2)
+    print(f"gradient 64^3 x {nt}: rel_max {rmax:.2e} rel_rms {rrms:.2e}; "
+          f"J {J.item():.6e} vs {J_ref:.6e}")
+    assert rmax <= 1e-3
+    assert J.item() == pytest.approx(J_ref, rel=1e-3)
