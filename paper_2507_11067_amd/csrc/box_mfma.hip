@@ -9,8 +9,8 @@
 //     T_{dz,dy}[m][x'] = c[dz][dy][x' - 4 - m]   (zero outside |x' - 4 - m| <= r),
 // and the 2r+1 dy blocks of one dz are laid side by side along K:
 //     D(16 x, 16 y) += [T_{dz,-r} .. T_{dz,r}] * [In_{z+dz}(rows y-r..) ; ... ; In(rows y+r..)]
-// K per dz is (2r+1)*24, padded to whole 32-wide steps of
-// v_mfma_f32_16x16x32_{bf16,f16}.
+// K per dz is (2r+1)*24, cut into 32-wide steps ("chunks") of
+// v_mfma_f32_16x16x32_{bf16,f16}; A = Toeplitz fragment, B = input fragment.
 //
 // FP32 accuracy from 16-bit multipliers: every operand x is split as x = hi + lo
 // (BF16: hi = RN(x), lo = RN(x - hi); FP16: the same after scaling by a power of
@@ -18,15 +18,17 @@
 // formed as hi*hi + hi*lo + lo*hi with FP32 accumulation (lo*lo is dropped).
 // The BF16X1 variant keeps hi*hi only.
 //
-// Work split.  A block owns a 16*NT (x) by 16 (y) output tile and streams z.
-// The NW waves of a block split K: wave w owns the 32-wide K steps (chunks)
-// c = w, w + NW, ...  and holds their Toeplitz fragments for all 2r+1 dz in
-// registers for the whole kernel.  One input plane at a time sits in LDS as
-// hi/lo 16-bit arrays (double-buffered); its B fragments are read once per
-// chunk and reused by every dz (input plane z' feeds output z' - dz), so each
-// wave keeps 2r+1 output accumulators in flight.  After each plane the oldest
-// output is complete in every wave; the NW partial tiles are summed through LDS
-// and written out.
+// Work split.  A block of 4 waves owns a (16*NT) x 64 output tile of the (x, y)
+// plane and streams a chunk of z.  All Toeplitz fragments (hi and lo, every dz
+// and chunk) are built once per block into LDS.  One input plane at a time sits
+// in LDS as hi/lo 16-bit arrays.  Each wave owns NT 16x16 tiles (16 rows) and
+// walks the full K: per chunk it loads the NT input fragments once and reuses
+// them for every dz and product (input plane z' feeds output z' - dz), and each
+// Toeplitz fragment pair it loads feeds NT tiles.  A wave therefore keeps 2r+1
+// output planes of accumulators in flight; after each input plane the oldest is
+// complete, is written, and the window shifts by one.  The next input plane is
+// requested from memory one plane ahead, so its latency hides behind a whole
+// plane of MFMA work.
 #include <hip/hip_runtime.h>
 
 #include "mms_internal.h"
@@ -38,23 +40,22 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+constexpr int NW = 4;    // waves per block
+constexpr int NT = 4;    // 16x16 tiles per wave along x
+constexpr int BXT = 16 * NT;
+constexpr int BYT = 16 * NW;
+
 struct MfmaArgs {
     Geom g;
     float c[729];      // [dz][dy][dx]
     float cscale;      // FP16 path: power-of-two scale of the weights
 };
 
-__device__ __forceinline__ uint32_t f2u(float x) { return __builtin_bit_cast(uint32_t, x); }
-__device__ __forceinline__ float u2f(uint32_t x) { return __builtin_bit_cast(float, x); }
-
-// FP32 -> BF16, round to nearest even (NaN kept quiet).
-__device__ __forceinline__ uint16_t bf16_rn(float x) {
-    uint32_t u = f2u(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// FP32 -> BF16 with round to nearest even (one v_cvt_pk_bf16_f32 on gfx950).
+__device__ __forceinline__ uint16_t bf16_rn(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ float bf16_f(uint16_t h) {
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
 }
-__device__ __forceinline__ float bf16_f(uint16_t h) { return u2f((uint32_t)h << 16); }
 
 template <int PREC>
 __device__ __forceinline__ void split(float x, float scale, uint16_t &hi, uint16_t &lo) {
@@ -81,25 +82,34 @@ __device__ __forceinline__ floatx4 mfma(const uint4 &a, const uint4 &b, floatx4 
     }
 }
 
-template <int R, int PREC, int NW, int NT>
-__global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
-    constexpr int Q = 2 * R + 1;          // output planes in flight
-    constexpr int WX = 24;                // x window per dy (16 + 2r <= 24, 8-aligned)
-    constexpr int KD = Q * WX;            // K per dz
-    constexpr int NCH = (KD + 31) / 32;   // 32-wide K steps per dz
-    constexpr int CPW = (NCH + NW - 1) / NW;
-    constexpr int LR = 16 + 2 * R;        // LDS rows per plane
-    constexpr int LP = 16 * NT + 8 + 8;   // LDS row pitch in 16-bit cells (8 spare for banks)
-    constexpr int NTH = 64 * NW;
-    constexpr int C4 = 4 * NT + 2;        // float4 per staged row
-    constexpr int NS = LR * C4;           // float4 per staged plane
-    constexpr int NSK = (NS + NTH - 1) / NTH;
-    constexpr bool SPLIT3 = PREC != MMS_BF16X1;
+template <int R>
+struct Shape {
+    static constexpr int Q = 2 * R + 1;             // output planes in flight, dz values
+    static constexpr int WX = 24;                   // x window per dy (16 + 2r <= 24)
+    static constexpr int NCH = (Q * WX + 31) / 32;  // 32-wide K steps per dz
+    static constexpr int NU = Q * NCH;              // Toeplitz fragment pairs
+    static constexpr int LR = BYT + 2 * R;          // LDS rows of a plane
+    static constexpr int LP = BXT + 8 + 8;          // LDS row pitch, 16-bit cells (8 spare)
+    static constexpr int C4 = BXT / 4 + 2;          // float4 per staged row
+    static constexpr int NS = LR * C4;              // float4 per staged plane
+    static constexpr int NSK = (NS + 64 * NW - 1) / (64 * NW);
+};
 
-    __shared__ __attribute__((aligned(16))) uint16_t dhi[2][LR][LP];
-    __shared__ __attribute__((aligned(16))) uint16_t dlo[2][LR][LP];
-    __shared__ floatx4 red[2][NW][NT][64];
-    __shared__ float smax[NW];
+template <int R>
+struct Smem {
+    uint4 afrag[Shape<R>::NU][2][64];   // [unit][hi, lo][lane]
+    uint16_t dhi[Shape<R>::LR][Shape<R>::LP];
+    uint16_t dlo[Shape<R>::LR][Shape<R>::LP];
+    float smax[NW];
+};
+
+template <int R, int PREC>
+__global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
+    using S = Shape<R>;
+    constexpr int Q = S::Q, NCH = S::NCH, C4 = S::C4, NS = S::NS, NSK = S::NSK, WX = S::WX;
+    constexpr int NTH = 64 * NW;
+    constexpr bool SPLIT3 = PREC != MMS_BF16X1;
+    __shared__ Smem<R> sm;
 
     const Geom &g = a.g;
     int b = mms_xcd_remap(blockIdx.x, gridDim.x);
@@ -110,7 +120,7 @@ __global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int xt = txi * 16 * NT, yt = tyi * 16;
+    const int xt = txi * BXT, yt = tyi * BYT;
     const int zb = zci * g.zchunk;
     const int ze = min(zb + g.zchunk, g.nz);
     const int nx4 = (g.nx + 3) & ~3;
@@ -144,11 +154,11 @@ __global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
         }
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-        if (lane == 0) smax[wave] = m;
+        if (lane == 0) sm.smax[wave] = m;
         __syncthreads();
-        m = smax[0];
+        m = sm.smax[0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) m = fmaxf(m, smax[w]);
+        for (int w = 1; w < NW; ++w) m = fmaxf(m, sm.smax[w]);
         if (m > 0.f && m < 3.0e38f) {
             int e;
             frexpf(m, &e);  // m = f 2^e, 0.5 <= f < 1
@@ -157,41 +167,34 @@ __global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
     }
     const float cscale = (PREC == MMS_FP16X3S) ? a.cscale : 1.0f;
 
-    // Toeplitz fragments of this wave's chunks for every dz (A operand, registers)
-    uint4 ahi[CPW][Q], alo[CPW][Q];
-    {
-        const int m = lane & 15, grp = lane >> 4;
+    // Toeplitz fragments of every (dz, chunk) into LDS (A operand)
+    for (int item = tid; item < S::NU * 64; item += NTH) {
+        const int u = item >> 6, l = item & 63;
+        const int dz = u / NCH, ch = u % NCH;
+        const int m = l & 15, grp = l >> 4;
+        uint16_t h[8], lo[8];
 #pragma unroll
-        for (int i = 0; i < CPW; ++i) {
-            const int ch = wave + NW * i;
-#pragma unroll
-            for (int dz = 0; dz < Q; ++dz) {
-                uint16_t h[8], l[8];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int k = 32 * ch + 8 * grp + j;
-                    const int dyi = k / WX, xp = k % WX;
-                    const int dx = xp - 4 - m;
-                    float v = 0.f;
-                    if (ch < NCH && dyi < Q && dx >= -R && dx <= R) v = a.c[(dz * Q + dyi) * Q + dx + R];
-                    split<PREC>(v, cscale, h[j], l[j]);
-                }
-                ahi[i][dz] = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16,
-                                        h[4] | (uint32_t)h[5] << 16, h[6] | (uint32_t)h[7] << 16);
-                alo[i][dz] = make_uint4(l[0] | (uint32_t)l[1] << 16, l[2] | (uint32_t)l[3] << 16,
-                                        l[4] | (uint32_t)l[5] << 16, l[6] | (uint32_t)l[7] << 16);
-            }
+        for (int j = 0; j < 8; ++j) {
+            const int k = 32 * ch + 8 * grp + j;
+            const int dyi = k / WX, xp = k % WX;
+            const int dx = xp - 4 - m;
+            float v = 0.f;
+            if (dyi < Q && dx >= -R && dx <= R) v = a.c[(dz * Q + dyi) * Q + dx + R];
+            split<PREC>(v, cscale, h[j], lo[j]);
         }
+        sm.afrag[u][0][l] = make_uint4(h[0] | (uint32_t)h[1] << 16, h[2] | (uint32_t)h[3] << 16,
+                                       h[4] | (uint32_t)h[5] << 16, h[6] | (uint32_t)h[7] << 16);
+        sm.afrag[u][1][l] = make_uint4(lo[0] | (uint32_t)lo[1] << 16, lo[2] | (uint32_t)lo[3] << 16,
+                                       lo[4] | (uint32_t)lo[5] << 16, lo[6] | (uint32_t)lo[7] << 16);
     }
 
     float4 stage[NSK];
     auto load_plane = [&](int z) {
         const float *p = g.in0 + (int64_t)z * sz;
 #pragma unroll
-        for (int k = 0; k < NSK; ++k)
-            stage[k] = guarded_load(p + s_off[k], s_ok[k], g.in0);
+        for (int k = 0; k < NSK; ++k) stage[k] = guarded_load(p + s_off[k], s_ok[k], g.in0);
     };
-    auto store_plane = [&](int buf) {
+    auto store_plane = [&]() {
 #pragma unroll
         for (int k = 0; k < NSK; ++k) {
             const int i = tid + k * NTH;
@@ -202,113 +205,104 @@ __global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
                 split<PREC>(stage[k].y, dscale, h1, l1);
                 split<PREC>(stage[k].z, dscale, h2, l2);
                 split<PREC>(stage[k].w, dscale, h3, l3);
-                *reinterpret_cast<uint2 *>(&dhi[buf][row][4 * col]) =
+                *reinterpret_cast<uint2 *>(&sm.dhi[row][4 * col]) =
                     make_uint2(h0 | (uint32_t)h1 << 16, h2 | (uint32_t)h3 << 16);
-                *reinterpret_cast<uint2 *>(&dlo[buf][row][4 * col]) =
+                *reinterpret_cast<uint2 *>(&sm.dlo[row][4 * col]) =
                     make_uint2(l0 | (uint32_t)l1 << 16, l2 | (uint32_t)l3 << 16);
             }
         }
     };
 
+    // acc[k][t] holds the partial sum of output plane zi - R + k
     floatx4 acc[Q][NT];
 #pragma unroll
     for (int s = 0; s < Q; ++s)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[s][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    // B-fragment coordinates of this lane: output row n, K group grp
-    const int n = lane & 15, grp = lane >> 4;
+    const int n = lane & 15, grp = lane >> 4;   // B fragment: output row n, K group grp
+    const int wrow = 16 * wave;
     const float outscale = 1.0f / (dscale * cscale);
 
     load_plane(z_first);
-    store_plane(0);
+    store_plane();
+    if (z_first + 1 < z_last) load_plane(z_first + 1);
     __syncthreads();
-    int buf = 0;
-    for (int zi = z_first; zi < z_last;) {
+    for (int zi = z_first; zi < z_last; ++zi) {
 #pragma unroll
-        for (int ph = 0; ph < Q; ++ph) {
-            if (zi < z_last) {
-                const bool more = zi + 1 < z_last;
-                if (more) load_plane(zi + 1);
+        for (int ch = 0; ch < NCH; ++ch) {
+            const int k0 = 32 * ch + 8 * grp;
+            const int dyi = k0 / WX, xg = (k0 % WX) / 8;
+            const bool kval = dyi < Q;
+            // the padded tail of K reads a valid row and is masked to zero
+            const uint32_t km = kval ? 0xffffffffu : 0u;
+            const int row = wrow + n + (kval ? dyi : 0);
+            uint4 bhi[NT], blo[NT];
 #pragma unroll
-                for (int i = 0; i < CPW; ++i) {
-                    const int ch = wave + NW * i;
-                    if (ch < NCH) {
-                        const int k0 = 32 * ch + 8 * grp;
-                        const int dyi = k0 / WX, xg = (k0 % WX) / 8;
-                        const bool kval = dyi < Q;
-                        const int row = kval ? n + dyi : 0;
-                        uint4 bhi[NT], blo[NT];
-#pragma unroll
-                        for (int t = 0; t < NT; ++t) {
-                            const uint4 z4 = make_uint4(0, 0, 0, 0);
-                            bhi[t] = kval ? *reinterpret_cast<const uint4 *>(&dhi[buf][row][16 * t + 8 * xg]) : z4;
-                            blo[t] = (SPLIT3 && kval)
-                                         ? *reinterpret_cast<const uint4 *>(&dlo[buf][row][16 * t + 8 * xg])
-                                         : z4;
-                        }
-                        // products outermost so that consecutive MFMAs feed independent
-                        // accumulators (2r+1 planes x NT tiles) and never wait on each other
-#pragma unroll
-                        for (int p = 0; p < (SPLIT3 ? 3 : 1); ++p) {
-#pragma unroll
-                            for (int dz = -R; dz <= R; ++dz) {
-                                const int zo = zi - dz;
-                                if (zo < zb || zo >= ze) continue;
-                                const int slot = (ph + R - dz + Q) % Q;
-                                const uint4 &af = (p == 2) ? alo[i][dz + R] : ahi[i][dz + R];
-#pragma unroll
-                                for (int t = 0; t < NT; ++t) {
-                                    const uint4 &bf = (p == 1) ? blo[t] : bhi[t];
-                                    acc[slot][t] = mfma<PREC>(af, bf, acc[slot][t]);
-                                }
-                            }
-                        }
-                    }
+            for (int t = 0; t < NT; ++t) {
+                const uint4 h = *reinterpret_cast<const uint4 *>(&sm.dhi[row][16 * t + 8 * xg]);
+                bhi[t] = make_uint4(h.x & km, h.y & km, h.z & km, h.w & km);
+                if constexpr (SPLIT3) {
+                    const uint4 l = *reinterpret_cast<const uint4 *>(&sm.dlo[row][16 * t + 8 * xg]);
+                    blo[t] = make_uint4(l.x & km, l.y & km, l.z & km, l.w & km);
                 }
-                // output plane zi - R is complete in this wave's share of K
-                const int zo = zi - R;
-                const bool emit = zo >= zb && zo < ze;
-                if (emit) {
+            }
 #pragma unroll
-                    for (int t = 0; t < NT; ++t) red[buf][wave][t][lane] = acc[ph][t];
+            for (int dz = -R; dz <= R; ++dz) {
+                // input plane zi feeds output zi - dz, held in acc[R - dz]
+                const uint4 ahi = sm.afrag[(dz + R) * NCH + ch][0][lane];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) acc[R - dz][t] = mfma<PREC>(ahi, bhi[t], acc[R - dz][t]);
+                if constexpr (SPLIT3) {
+                    const uint4 alo = sm.afrag[(dz + R) * NCH + ch][1][lane];
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[R - dz][t] = mfma<PREC>(ahi, blo[t], acc[R - dz][t]);
+#pragma unroll
+                    for (int t = 0; t < NT; ++t)
+                        acc[R - dz][t] = mfma<PREC>(alo, bhi[t], acc[R - dz][t]);
                 }
-#pragma unroll
-                for (int t = 0; t < NT; ++t) acc[ph][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-                if (more) store_plane(buf ^ 1);
-                __syncthreads();
-                if (emit) {
-                    for (int i = tid; i < NT * 64; i += NTH) {
-                        const int t = i / 64, l = i % 64;
-                        floatx4 s = red[buf][0][t][l];
-#pragma unroll
-                        for (int w = 1; w < NW; ++w) s += red[buf][w][t][l];
-                        const int y = yt + (l & 15);
-                        const int x = xt + 16 * t + 4 * (l >> 4);
-                        if (y < g.ny && x < g.nx) {
-                            float *po = g.out0 + (int64_t)zo * sz + (int64_t)y * sy + x;
-                            const float4 o = make_float4(s[0] * outscale, s[1] * outscale,
-                                                         s[2] * outscale, s[3] * outscale);
-                            if (x + 3 < g.nx) {
-                                *reinterpret_cast<float4 *>(po) = o;
-                            } else {
-                                if (x + 0 < g.nx) po[0] = o.x;
-                                if (x + 1 < g.nx) po[1] = o.y;
-                                if (x + 2 < g.nx) po[2] = o.z;
-                            }
-                        }
-                    }
-                }
-                buf ^= 1;
-                ++zi;
             }
         }
+        // output plane zi - R is complete (outputs outside [zb, ze) are dropped)
+        const int zo = zi - R;
+        if (zo >= zb && zo < ze) {
+            const int y = yt + wrow + n;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int x = xt + 16 * t + 4 * grp;
+                if (y < g.ny && x < g.nx) {
+                    float *po = g.out0 + (int64_t)zo * sz + (int64_t)y * sy + x;
+                    const floatx4 s = acc[0][t];
+                    const float4 o = make_float4(s[0] * outscale, s[1] * outscale,
+                                                 s[2] * outscale, s[3] * outscale);
+                    if (x + 3 < g.nx) {
+                        *reinterpret_cast<float4 *>(po) = o;
+                    } else {
+                        if (x + 0 < g.nx) po[0] = o.x;
+                        if (x + 1 < g.nx) po[1] = o.y;
+                        if (x + 2 < g.nx) po[2] = o.z;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int s = 0; s + 1 < Q; ++s)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[s][t] = acc[s + 1][t];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[Q - 1][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        __syncthreads();   // every wave is done with plane zi
+        if (zi + 1 < z_last) {
+            store_plane();                              // plane zi + 1
+            if (zi + 2 < z_last) load_plane(zi + 2);    // requested a whole plane ahead
+        }
+        __syncthreads();
     }
 }
 
 template <int R, int PREC>
 int launch_rp(const float *in, float *out, const mms_grid *gd, const float *coeffs, hipStream_t s) {
-    constexpr int NW = 4, NT = 2;
     constexpr int Q = 2 * R + 1;
     MfmaArgs a{};
     Geom &g = a.g;
@@ -320,13 +314,14 @@ int launch_rp(const float *in, float *out, const mms_grid *gd, const float *coef
     g.nz = (int)gd->nz;
     g.sy = gd->sy;
     g.sz = gd->sz;
-    g.ntx = (g.nx + 16 * NT - 1) / (16 * NT);
-    g.nty = (g.ny + 15) / 16;
+    g.ntx = (g.nx + BXT - 1) / BXT;
+    g.nty = (g.ny + BYT - 1) / BYT;
     int zc = zchunk_override(MMS_BOX, PREC);
     if (zc <= 0) {
+        // one block per CU: about 256 blocks, chunks of at most 128 planes
         const int64_t cols = (int64_t)g.ntx * g.nty;
-        zc = (int)((int64_t)g.nz * cols / 2048);
-        zc = zc < 32 ? 32 : zc;
+        zc = (int)((int64_t)g.nz * cols / 256);
+        zc = zc < 32 ? 32 : (zc > 128 ? 128 : zc);
     }
     g.zchunk = zc;
     g.nzc = (g.nz + zc - 1) / zc;
@@ -344,8 +339,7 @@ int launch_rp(const float *in, float *out, const mms_grid *gd, const float *coef
     }
     const int64_t nblk = (int64_t)g.ntx * g.nty * g.nzc;
     if (nblk > 0x7fffffff) return MMS_EINVAL;
-    hipLaunchKernelGGL((box_mfma_kernel<R, PREC, NW, NT>), dim3((unsigned)nblk), dim3(64 * NW), 0,
-                       s, a);
+    hipLaunchKernelGGL((box_mfma_kernel<R, PREC>), dim3((unsigned)nblk), dim3(64 * NW), 0, s, a);
     return check_launch("box_mfma_kernel");
 }
 

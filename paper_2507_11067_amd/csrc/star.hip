@@ -220,10 +220,11 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     g.nty = (g.ny + TY * NY - 1) / (TY * NY);
     int zc = zchunk_override(MMS_STAR, MMS_FP32);
     if (zc <= 0) {
-        // aim for about 2048 blocks, keeping chunks long enough to amortise the 2r-plane fill
+        // about 512 blocks (two per CU) with chunks of at most 128 planes: long chunks
+        // amortise the 2r-plane fill and the z-halo re-read of each chunk
         const int64_t cols = (int64_t)g.ntx * g.nty;
-        zc = (int)((int64_t)g.nz * cols / 2048);
-        zc = zc < 16 ? 16 : zc;
+        zc = (int)((int64_t)g.nz * cols / 512);
+        zc = zc < 16 ? 16 : (zc > 128 ? 128 : zc);
     }
     g.zchunk = zc;
     g.nzc = (g.nz + zc - 1) / zc;
