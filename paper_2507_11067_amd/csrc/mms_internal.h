@@ -32,6 +32,17 @@ struct Geom {
 
 int zchunk_override(int shape, int precision);
 
+// z-chunk length so that (x, y) tiles times z chunks fill `slots` concurrent
+// blocks in one wave (slots = CUs x blocks per CU), clamped to [zmin, zmax].
+inline int pick_zchunk(int nz, int64_t cols, int64_t slots, int zmin, int zmax) {
+    int64_t chunks = cols > 0 ? slots / cols : 1;
+    if (chunks < 1) chunks = 1;
+    int64_t zc = (nz + chunks - 1) / chunks;
+    if (zc < zmin) zc = zmin;
+    if (zc > zmax) zc = zmax;
+    return (int)zc;
+}
+
 // Sweep launchers (host), one per kernel family.  coeffs is a host array.
 int launch_star(const float *in, float *out, const mms_grid *g, int r, const float *coeffs,
                 hipStream_t s);

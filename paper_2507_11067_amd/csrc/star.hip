@@ -8,10 +8,13 @@
 //  * every lane owns 4 consecutive x (one 16-byte load) in NY rows and keeps
 //    the 2r+1 z planes of those cells in a register queue, so the z-axis terms
 //    never touch LDS;
-//  * the current plane of the tile, with 4 cells of x halo and r rows of y
-//    halo, sits in LDS (double-buffered, one barrier per plane); the x and y
-//    terms read 16-byte words from it;
-//  * the next planes are requested from memory one iteration ahead;
+//  * the tile of each plane, with 4 cells of x halo and r rows of y halo, is
+//    requested when the plane enters the queue (together with the neighbouring
+//    tiles, which read the same rows as their own cells, so the shared rows are
+//    fetched from HBM once and served from L2) and parked in an LDS ring of
+//    r+2 planes until it becomes the centre plane; the x and y terms read
+//    16-byte words from it; one barrier per plane;
+//  * outputs are written with streaming (non-temporal) stores;
 //  * the z loop is unrolled by the queue length so the queue rotates by
 //    renaming registers instead of moving them.
 // Block indices are remapped so that each XCD works on one contiguous range of
@@ -21,6 +24,8 @@
 namespace mms {
 namespace {
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 struct StarArgs {
     Geom g;
     float c[3][9];  // axis z, y, x; k + r
@@ -29,6 +34,7 @@ struct StarArgs {
 template <int R, int TX, int TY, int NY>
 __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
     constexpr int Q = 2 * R + 1;     // planes in the register queue
+    constexpr int NR = R + 2;        // planes in the LDS ring: z .. z+R+1
     constexpr int BX = 4 * TX;       // tile width in cells
     constexpr int BY = TY * NY;      // tile height in rows
     constexpr int LW4 = TX + 2;      // LDS row in float4 (one float4 of halo each side)
@@ -36,7 +42,7 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
     constexpr int NT = TX * TY;
     constexpr int NH = 2 * R * LW4 + 2 * BY;  // halo float4 per plane
     constexpr int NHK = (NH + NT - 1) / NT;
-    __shared__ float4 tile[2][LH][LW4];
+    __shared__ float4 ring[NR][LH][LW4];
 
     const Geom &g = a.g;
     int b = mms_xcd_remap(blockIdx.x, gridDim.x);
@@ -93,17 +99,15 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
     auto own_load = [&](int z, float4 *dst) {
         const float *p = in0 + (int64_t)z * sz + (int64_t)y0 * sy + x0;
 #pragma unroll
-        for (int j = 0; j < NY; ++j)
-            dst[j] = guarded_load(p + j * sy, own_ok[j], in0);
+        for (int j = 0; j < NY; ++j) dst[j] = guarded_load(p + j * sy, own_ok[j], in0);
     };
     auto halo_load = [&](int z, float4 *dst) {
         const float *p = in0 + (int64_t)z * sz;
 #pragma unroll
-        for (int k = 0; k < NHK; ++k)
-            dst[k] = guarded_load(p + h_off[k], h_ok[k], in0);
+        for (int k = 0; k < NHK; ++k) dst[k] = guarded_load(p + h_off[k], h_ok[k], in0);
     };
-    auto lds_store = [&](int buf, const float4 *own, const float4 *halo) {
-        float4 *t = &tile[buf][0][0];
+    auto ring_store = [&](int slot, const float4 *own, const float4 *halo) {
+        float4 *t = &ring[slot][0][0];
 #pragma unroll
         for (int j = 0; j < NY; ++j) t[(R + ty * NY + j) * LW4 + tx + 1] = own[j];
 #pragma unroll
@@ -113,27 +117,33 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
 
     float4 q[Q][NY];
     float4 hreg[NHK];
-    // prologue: planes zb-R .. zb+R into the queue, plane zb into LDS buffer 0
+    // prologue: planes zb-R .. zb+R into the queue; the tiles of planes zb .. zb+R
+    // (own cells and halo) into the LDS ring
 #pragma unroll
     for (int i = 0; i < Q; ++i) own_load(zb - R + i, q[i]);
-    halo_load(zb, hreg);
-    lds_store(0, q[R], hreg);
+#pragma unroll
+    for (int i = 0; i <= R; ++i) {
+        halo_load(zb + i, hreg);
+        ring_store((zb + i) % NR, q[R + i], hreg);
+    }
     __syncthreads();
 
     const float *c = &a.c[0][0];
     float *out0 = g.out0;
-    int buf = 0;
     for (int z = zb; z < ze;) {
 #pragma unroll
         for (int ph = 0; ph < Q; ++ph) {
             if (z < ze) {
+                // the tile of plane z+R+1 is requested now, alongside the neighbouring
+                // tiles that read the same rows as their own cells, and parked in the
+                // ring until it becomes the centre plane
                 const bool more = z + 1 < ze;
                 float4 nq[NY];
                 if (more) {
                     own_load(z + R + 1, nq);
-                    halo_load(z + 1, hreg);
+                    halo_load(z + R + 1, hreg);
                 }
-                const float4 *t = &tile[buf][0][0];
+                const float4 *t = &ring[z % NR][0][0];
 #pragma unroll
                 for (int j = 0; j < NY; ++j) {
                     const float4 ctr = q[(ph + R) % Q][j];
@@ -182,7 +192,9 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
                     if (y < g.ny && x0 < g.nx) {
                         float *po = out0 + (int64_t)z * sz + (int64_t)y * sy + x0;
                         if (x0 + 3 < g.nx) {
-                            *reinterpret_cast<float4 *>(po) = make_float4(o[0], o[1], o[2], o[3]);
+                            // streaming store: the output is not read again by this sweep
+                            const f4v v = {o[0], o[1], o[2], o[3]};
+                            __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(po));
                         } else {
 #pragma unroll
                             for (int e = 0; e < 4; ++e)
@@ -191,12 +203,11 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
                     }
                 }
                 if (more) {
-                    lds_store(buf ^ 1, q[(ph + R + 1) % Q], hreg);
+                    ring_store((z + R + 1) % NR, nq, hreg);
 #pragma unroll
                     for (int j = 0; j < NY; ++j) q[ph][j] = nq[j];
                 }
                 __syncthreads();
-                buf ^= 1;
                 ++z;
             }
         }
@@ -205,7 +216,7 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
 
 template <int R>
 int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeffs, hipStream_t s) {
-    constexpr int TX = 32, TY = 8, NY = 2;
+    constexpr int TX = 64, TY = 16, NY = 1;
     StarArgs a{};
     Geom &g = a.g;
     g.H = gd->halo;
@@ -220,11 +231,9 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     g.nty = (g.ny + TY * NY - 1) / (TY * NY);
     int zc = zchunk_override(MMS_STAR, MMS_FP32);
     if (zc <= 0) {
-        // about 512 blocks (two per CU) with chunks of at most 128 planes: long chunks
-        // amortise the 2r-plane fill and the z-halo re-read of each chunk
-        const int64_t cols = (int64_t)g.ntx * g.nty;
-        zc = (int)((int64_t)g.nz * cols / 512);
-        zc = zc < 16 ? 16 : (zc > 128 ? 128 : zc);
+        // one block per CU (the LDS ring fills most of a CU's LDS): enough z chunks
+        // to give every CU one block, chunks of 8 to 128 planes
+        zc = pick_zchunk(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128);
     }
     g.zchunk = zc;
     g.nzc = (g.nz + zc - 1) / zc;

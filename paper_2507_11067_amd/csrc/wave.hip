@@ -64,7 +64,8 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     constexpr int NT = TX * TY;
     constexpr int NH = 2 * R * LW4 + 2 * BY;
     constexpr int NHK = (NH + NT - 1) / NT;
-    __shared__ float4 tile[NF][2][LH][LW4];
+    constexpr int NR = R + 2;   // LDS ring: planes z .. z+R+1
+    __shared__ float4 ring[NF][NR][LH][LW4];
     __shared__ double sred[NT / 64];
 
     const Geom &g = a.g;
@@ -154,11 +155,12 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
         }
         return ld(f == 0 ? a.f0 : a.fu, z, h_off[k], h_ok[k]);
     };
-    auto lds_store = [&](int buf, float4 (*own)[Q], int slot, float4 (*halo)[NHK]) {
+    // tile of one plane (own cells + halo) into ring slot `slot`
+    auto ring_store = [&](int slot, const float4 *own, float4 (*halo)[NHK]) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            float4 *t = &tile[f][buf][0][0];
-            t[(R + ty) * LW4 + tx + 1] = own[f][slot];
+            float4 *t = &ring[f][slot][0][0];
+            t[(R + ty) * LW4 + tx + 1] = own[f];
 #pragma unroll
             for (int k = 0; k < NHK; ++k)
                 if (tid + k * NT < NH) t[h_lds[k]] = halo[f][k];
@@ -167,14 +169,22 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
 
     float4 q[NF][Q];
     float4 hreg[NF][NHK];
+    // prologue: planes zb-R .. zb+R into the queue; tiles of planes zb .. zb+R into the ring
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int i = 0; i < Q; ++i) q[f][i] = own_field(f, zb - R + i);
 #pragma unroll
-        for (int k = 0; k < NHK; ++k) hreg[f][k] = halo_field(f, zb, k);
+    for (int i = 0; i <= R; ++i) {
+        float4 own[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            own[f] = q[f][R + i];
+#pragma unroll
+            for (int k = 0; k < NHK; ++k) hreg[f][k] = halo_field(f, zb + i, k);
+        }
+        ring_store((zb + i) % NR, own, hreg);
     }
-    lds_store(0, q, R, hreg);
     // point-wise operands of the first plane
     float4 pw0 = ld(a.p0, zb, own_off, own_ok);
     float4 pw1 = (MODE == MODE_ADJ) ? ld(a.f0, zb, own_off, own_ok) : ld(a.c2, zb, own_off, own_ok);
@@ -183,7 +193,6 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     const float *c = a.c;
     const float srcv = (MODE == MODE_FWD && a.src) ? *a.src : 0.f;
     double esum = 0.0;
-    int buf = 0;
     for (int z = zb; z < ze;) {
 #pragma unroll
         for (int ph = 0; ph < Q; ++ph) {
@@ -192,11 +201,13 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                 float4 nq[NF];
                 float4 npw0 = zero4, npw1 = zero4;
                 if (more) {
+                    // the tile of plane z+R+1 is requested together with the neighbouring
+                    // tiles that read the same rows, and parked in the ring
 #pragma unroll
                     for (int f = 0; f < NF; ++f) {
                         nq[f] = own_field(f, z + R + 1);
 #pragma unroll
-                        for (int k = 0; k < NHK; ++k) hreg[f][k] = halo_field(f, z + 1, k);
+                        for (int k = 0; k < NHK; ++k) hreg[f][k] = halo_field(f, z + R + 1, k);
                     }
                     npw0 = ld(a.p0, z + 1, own_off, own_ok);
                     npw1 = (MODE == MODE_ADJ) ? ld(a.f0, z + 1, own_off, own_ok)
@@ -205,7 +216,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                 float o[NF][4];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    const float4 *t = &tile[f][buf][0][0];
+                    const float4 *t = &ring[f][z % NR][0][0];
                     const float4 ctr = q[f][(ph + R) % Q];
                     float s[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -301,14 +312,13 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                     }
                 }
                 if (more) {
-                    lds_store(buf ^ 1, q, (ph + R + 1) % Q, hreg);
+                    ring_store((z + R + 1) % NR, nq, hreg);
 #pragma unroll
                     for (int f = 0; f < NF; ++f) q[f][ph] = nq[f];
                     pw0 = npw0;
                     pw1 = npw1;
                 }
                 __syncthreads();
-                buf ^= 1;
                 ++z;
             }
         }
@@ -373,26 +383,33 @@ __global__ void sum_partials_kernel(const double *p, int n, double *out) {
     if (threadIdx.x == 0) *out = s[0];
 }
 
-constexpr int WTX = 32, WTY = 8;
+// Tile shapes: one stencil field -> 256 x 16 cells per block; two fields (adjoint with
+// gradient) -> 128 x 16.  Either way the LDS ring fills most of a CU's LDS, so one
+// block runs per CU.
+template <int MODE, bool GRAD>
+struct Cfg {
+    static constexpr bool TWO = MODE == MODE_ADJ && GRAD;
+    static constexpr int TX = TWO ? 32 : 64;
+    static constexpr int TY = 16;
+};
 
-void fill_geom(Geom &g, const mms_grid *gd, int zdiv) {
+template <int MODE, bool GRAD>
+void fill_geom(Geom &g, const mms_grid *gd) {
+    constexpr int TX = Cfg<MODE, GRAD>::TX, TY = Cfg<MODE, GRAD>::TY;
     g.H = gd->halo;
     g.nx = (int)gd->nx;
     g.ny = (int)gd->ny;
     g.nz = (int)gd->nz;
     g.sy = gd->sy;
     g.sz = gd->sz;
-    g.ntx = (g.nx + 4 * WTX - 1) / (4 * WTX);
-    g.nty = (g.ny + WTY - 1) / WTY;
-    const int64_t cols = (int64_t)g.ntx * g.nty;
-    int zc = (int)((int64_t)g.nz * cols / zdiv);
-    g.zchunk = zc < 16 ? 16 : zc;
+    g.ntx = (g.nx + 4 * TX - 1) / (4 * TX);
+    g.nty = (g.ny + TY - 1) / TY;
+    g.zchunk = pick_zchunk(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128);
     g.nzc = (g.nz + g.zchunk - 1) / g.zchunk;
 }
 
 WaveArgs base_args(const mms_wave *w) {
     WaveArgs a{};
-    fill_geom(a.g, &w->g, 2048);
     const int r = w->radius;
     for (int k = -r; k <= r; ++k) a.c[k + r] = w->lap[k < 0 ? -k : k];
     a.sponge_w = w->sponge_width;
@@ -405,15 +422,17 @@ WaveArgs base_args(const mms_wave *w) {
 }
 
 template <int MODE, bool GRAD>
-int launch_mode(const WaveArgs &a, int r, hipStream_t s) {
+int launch_mode(WaveArgs &a, const mms_grid *gd, int r, hipStream_t s) {
+    constexpr int TX = Cfg<MODE, GRAD>::TX, TY = Cfg<MODE, GRAD>::TY;
+    fill_geom<MODE, GRAD>(a.g, gd);
     const int64_t nblk = (int64_t)a.g.ntx * a.g.nty * a.g.nzc;
     if (nblk > 0x7fffffff) return MMS_EINVAL;
-    const dim3 grid((unsigned)nblk), block(WTX * WTY);
+    const dim3 grid((unsigned)nblk), block(TX * TY);
     switch (r) {
-        case 1: hipLaunchKernelGGL((wave_kernel<1, MODE, GRAD, WTX, WTY>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((wave_kernel<2, MODE, GRAD, WTX, WTY>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((wave_kernel<3, MODE, GRAD, WTX, WTY>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((wave_kernel<4, MODE, GRAD, WTX, WTY>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((wave_kernel<1, MODE, GRAD, TX, TY>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((wave_kernel<2, MODE, GRAD, TX, TY>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((wave_kernel<3, MODE, GRAD, TX, TY>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((wave_kernel<4, MODE, GRAD, TX, TY>), grid, block, 0, s, a); break;
         default: return MMS_EUNSUPPORTED;
     }
     return check_launch("wave_kernel");
@@ -433,7 +452,7 @@ int wave_step(const mms_wave *w, int n, const float *up, const float *uc, float 
     a.src_z = (int)w->src_z;
     a.src_y = (int)w->src_y;
     a.src_x = (int)w->src_x;
-    return launch_mode<MODE_FWD, false>(a, w->radius, s);
+    return launch_mode<MODE_FWD, false>(a, &w->g, w->radius, s);
 }
 
 int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1, float *l0,
@@ -444,6 +463,7 @@ int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1
     a.out = l0 + o;
     a.resid = resid ? resid + (int64_t)n * w->g.ny * w->g.nx : nullptr;
     if (n == 0) {
+        fill_geom<MODE_ADJ, false>(a.g, &w->g);
         const int64_t np = w->g.nx * w->g.ny * w->g.nz;
         const unsigned nb = (unsigned)((np + 255) / 256);
         hipLaunchKernelGGL(adjoint_first_kernel, dim3(nb), dim3(256), 0, s, a);
@@ -453,9 +473,9 @@ int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1
     if (grad) {
         a.fu = un + o;
         a.acc64 = grad;
-        return launch_mode<MODE_ADJ, true>(a, w->radius, s);
+        return launch_mode<MODE_ADJ, true>(a, &w->g, w->radius, s);
     }
-    return launch_mode<MODE_ADJ, false>(a, w->radius, s);
+    return launch_mode<MODE_ADJ, false>(a, &w->g, w->radius, s);
 }
 
 int wave_record(const mms_wave *w, int n, const float *u, hipStream_t s) {
@@ -482,17 +502,19 @@ int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *o
     a.f0 = un + o;
     a.p0 = unp1 + o;
     a.partials = partials;
+    fill_geom<MODE_ENERGY, false>(a.g, &w->g);
     const int64_t nblk = (int64_t)a.g.ntx * a.g.nty * a.g.nzc;
     if (nblk > npartials) return MMS_ENOMEM;
-    int rc = launch_mode<MODE_ENERGY, false>(a, w->radius, s);
+    int rc = launch_mode<MODE_ENERGY, false>(a, &w->g, w->radius, s);
     if (rc) return rc;
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partials, (int)nblk, out);
     return check_launch("sum_partials_kernel");
 }
 
 int64_t wave_energy_blocks(const mms_wave *w) {
-    WaveArgs a = base_args(w);
-    return (int64_t)a.g.ntx * a.g.nty * a.g.nzc;
+    Geom g{};
+    fill_geom<MODE_ENERGY, false>(g, &w->g);
+    return (int64_t)g.ntx * g.nty * g.nzc;
 }
 
 }  // namespace mms
