@@ -56,7 +56,10 @@ def parse():
                    "box4_fp16x3s|box3_bf16x3|wave|copy")
     p.add_argument("--skip", default="", help="comma list of extras to skip: "
                    "split,rtm,gradient,cpu,check")
-    p.add_argument("--cpu-planes", type=int, default=0, help="oracle sample depth (0 = auto)")
+    p.add_argument("--cpu-planes", type=int, default=0, help="oracle sample depth (0 = full grid)")
+    p.add_argument("--collect", action="store_true",
+                   help="run rocprofv3 (kernel trace, FETCH_SIZE, WRITE_SIZE) as child processes "
+                        "over the headline kernels and a plain copy, and write profiles/")
     return p.parse_args()
 
 
@@ -102,6 +105,8 @@ def main():
               "(the multi-GPU z-slab decomposition is a design note, not built)",
               file=sys.stderr)
         sys.exit(2)
+    if args.collect:
+        return collect_counters(args)
     import torch
     import paper_2507_11067_amd as mms
     import synth
@@ -186,7 +191,17 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["kernel"] = {"star": "star_kernel<4>", "box2": "box_valu_kernel<2>",
                       "box4": "box_valu_kernel<4>"}[dom]
-    roof["traffic"] = None
+    roof["traffic"] = traffic_for(dom)
+    rooflines = {}
+    for name, (bound, bytes_pt, flop_pt) in per.items():
+        k = kernels[name]
+        if bound == "hbm":
+            rooflines[name] = {"bound": "hbm", "achieved": k["gbs"], "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": k["hbm_frac"], "traffic": traffic_for(name)}
+        else:
+            rooflines[name] = {"bound": "alu", "achieved": k["tflops"], "peak": FP32_VALU_PEAK_TF,
+                               "unit": "TFLOP/s", "frac": k["valu_frac"],
+                               "traffic": traffic_for(name)}
 
     result = {
         "metric": METRIC, "value": value, "unit": "Gpoints/s", "n_gpus": 1,
@@ -197,6 +212,7 @@ def main():
                                "radius-4 box (4-cell zero halo, uniform [-1,1] seed 2)",
                    "grid": [n, n, n], "halo": 4, "points_per_step": 3 * pts},
         "roofline": roof,
+        "rooflines": rooflines,
         "kernels": kernels,
     }
     if "split" not in skip:
@@ -348,13 +364,103 @@ def bench_gradient(torch, mms, synth, dev, n=256, nt=1000, K=50):
     rhs = mms.dot(u0, lam[0], grid) + mms.dot(u1, lam[1], grid)
     res["dot_test"] = {"lhs": lhs, "rhs": rhs, "rel": abs(lhs - rhs) / abs(lhs)}
     log(f"[bench] dot test rel {res['dot_test']['rel']:.2e}")
+    res["finite_differences"], res["taylor"] = gradient_checks(torch, mms, synth, prob, m, d_obs,
+                                                               grid, dev)
     return res
+
+
+def gradient_checks(torch, mms, synth, prob, m, d_obs, grid, dev, npts=16, seed=84):
+    """Central finite differences of J at 16 points drawn from the top decile of |dJ/dm|
+    (eps = 1e-2 m_i), and a Taylor test along a smooth direction."""
+    n, nt = grid.nx, prob.nt
+    traces = torch.zeros((nt, grid.ny, grid.nx), device=dev)
+    bufs = [grid.zeros(dev) for _ in range(3)]
+    jout = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def J_of(mt):
+        w = prob.wave(mt, traces)
+        for b_ in bufs:
+            b_.zero_()
+        w.record(0, bufs[0])
+        w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+        return mms.flat_misfit(traces, d_obs, out=jout).item()
+
+    g = m.grad.detach()
+    gi = grid.interior(g).cpu().numpy()
+    mi = grid.interior(m.detach()).cpu().numpy()
+    rng = np.random.default_rng(seed)
+    cut = np.quantile(np.abs(gi), 0.9)
+    cand = np.argwhere(np.abs(gi) >= cut)
+    pick = cand[rng.choice(len(cand), npts, replace=False)]
+    md = m.detach()
+    # (a) one cell per point: in FP32 the trace change of a single-cell perturbation sits
+    #     near the rounding level of the traces, so these numbers are reported, not gated;
+    # (b) a Gaussian bump (sigma = 2 cells, 13^3 support) centred on each point: the
+    #     directional derivative <g, bump> is compared with the central difference.
+    sig, hw = 2.0, 6
+    ax = np.arange(-hw, hw + 1)
+    bump = np.exp(-(ax[:, None, None] ** 2 + ax[None, :, None] ** 2 + ax[None, None, :] ** 2)
+                  / (2 * sig * sig))
+    fd_rows = []
+    for z_, y_, x_ in pick:
+        z_, y_, x_ = (int(min(max(v, hw), n - 1 - hw)) for v in (z_, y_, x_))
+        mi_c = float(mi[z_, y_, x_])
+        row = {"point": [z_, y_, x_]}
+        idx = (z_ + 4, y_ + 4, x_ + 4)
+        eps = 5e-2 * mi_c
+        mp = md.clone()
+        mp[idx] += eps
+        jp = J_of(mp)
+        mp[idx] -= 2 * eps
+        jm = J_of(mp)
+        ga = float(gi[z_, y_, x_])
+        row["cell_fd"], row["cell_adjoint"] = (jp - jm) / (2 * eps), ga
+        row["cell_rel"] = abs(row["cell_fd"] - ga) / abs(ga)
+        sl = (slice(z_ + 4 - hw, z_ + 5 + hw), slice(y_ + 4 - hw, y_ + 5 + hw),
+              slice(x_ + 4 - hw, x_ + 5 + hw))
+        db = torch.from_numpy((1e-2 * mi_c * bump).astype(np.float32)).to(dev)
+        mp = md.clone()
+        mp[sl] += db
+        jp = J_of(mp)
+        mp[sl] -= 2 * db
+        jm = J_of(mp)
+        fdb = (jp - jm) / 2.0
+        gdb = float(np.sum(gi[z_ - hw:z_ + hw + 1, y_ - hw:y_ + hw + 1, x_ - hw:x_ + hw + 1]
+                           .astype(np.float64) * db.cpu().numpy().astype(np.float64)))
+        row["bump_fd"], row["bump_adjoint"] = fdb, gdb
+        row["bump_rel"] = abs(fdb - gdb) / abs(gdb)
+        fd_rows.append(row)
+    cr = [r["cell_rel"] for r in fd_rows]
+    br = [r["bump_rel"] for r in fd_rows]
+    fdres = {"points": fd_rows, "cell_eps_rel": 5e-2, "bump_sigma_cells": sig,
+             "bump_amp_rel": 1e-2, "cell_rel_median": float(np.median(cr)),
+             "cell_rel_max": float(np.max(cr)), "bump_rel_median": float(np.median(br)),
+             "bump_rel_max": float(np.max(br))}
+    log(f"[bench] FD at 16 top-decile points: single cell rel median {fdres['cell_rel_median']:.2e}"
+        f" max {fdres['cell_rel_max']:.2e}; bump rel median {fdres['bump_rel_median']:.2e} "
+        f"max {fdres['bump_rel_max']:.2e}")
+    # Taylor test along a smooth direction dm (max |dm| = 1 % of mean m)
+    dm = torch.from_numpy(synth.smooth_random_grid(85, n, n, n, sigma=4.0)).to(dev)
+    scale = 0.01 * float(np.mean(mi))
+    dm.mul_(scale)
+    gdm = mms.dot(g, dm, grid)
+    J0 = J_of(md)
+    rows = []
+    for eps in (1.0, 0.5, 0.25, 0.125):
+        Je = J_of(md + eps * dm)
+        rows.append({"eps": eps, "J": Je, "first_order_ratio": (Je - J0) / (eps * gdm),
+                     "remainder": abs(Je - J0 - eps * gdm)})
+    for a_, b_ in zip(rows, rows[1:]):
+        b_["remainder_ratio"] = a_["remainder"] / b_["remainder"] if b_["remainder"] else None
+    log("[bench] Taylor: " + ", ".join(f"eps {r['eps']}: J'/gdm {r['first_order_ratio']:.5f}"
+                                       for r in rows))
+    return fdres, {"J0": J0, "g_dot_dm": gdm, "rows": rows}
 
 
 def cpu_baseline(x_np, n, c_star, c_box2, c_box4, planes):
     """FP64 oracle on the host cores over a slab of the headline input."""
     import oracle
-    nz = planes if planes > 0 else 32
+    nz = planes if planes > 0 else n
     nz = min(nz, n)
     slab = np.ascontiguousarray(x_np[:nz + 8].astype(np.float64))  # planes -4 .. nz+3
     cores = len(os.sched_getaffinity(0))
@@ -371,6 +477,146 @@ def cpu_baseline(x_np, n, c_star, c_box2, c_box4, planes):
             "kind": "oracle",
             "sample": f"one sweep each of star r4, box r2, box r4 (FP64) over a {n}x{n}x{nz} "
                       f"slab of the same input; {dt:.1f} s"}
+
+
+# ---------------------------------------------------------------- counters
+PROFILES = os.path.join(ROOT, "profiles")
+COUNTERS_JSON = os.path.join(PROFILES, "counters_512.json")
+# kernel (bench --only name) -> (source file, kernel symbol substring, algorithmic bytes per point)
+COUNTED = {
+    "copy": (None, "copyBuffer", 8.0),
+    "star": ("star.hip", "star_kernel<4", 8.0),
+    "box2": ("box_valu.hip", "box_valu_kernel<2", 8.0),
+    "box4": ("box_valu.hip", "box_valu_kernel<4", 8.0),
+    "box4_bf16x3": ("box_mfma.hip", "box_mfma_kernel<4, 1>", 8.0),
+    "box3_bf16x3": ("box_mfma.hip", "box_mfma_kernel<3, 1>", 8.0),
+}
+
+
+def source_sha(fname):
+    import hashlib
+    if fname is None:
+        return None
+    path = os.path.join(ROOT, "paper_2507_11067_amd", "csrc", fname)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(name):
+    """HBM bytes per launch from the committed counter summary, if that summary was taken
+    on the current source of the kernel (else None)."""
+    try:
+        d = json.load(open(COUNTERS_JSON))
+    except (OSError, ValueError):
+        return None
+    e = d.get("kernels", {}).get(name)
+    if not e or e.get("source_sha") != source_sha(COUNTED[name][0]):
+        return None
+    return e["hbm_bytes_per_launch"]
+
+
+def _counter_mean(csv_path, substr):
+    import csv
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
+            if substr in r["Kernel_Name"]]
+    return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+
+def _stats_mean_ns(csv_path, substr):
+    import csv
+    for r in csv.DictReader(open(csv_path)):
+        if substr in r["Name"]:
+            return float(r["AverageNs"]), int(r["Calls"])
+    return None, 0
+
+
+def collect_counters(args):
+    """rocprofv3 runs (each a child process of this one, which never touches the GPU):
+    a kernel trace of the headline bench command, then FETCH_SIZE and WRITE_SIZE per kernel.
+    The copy kernel of known size calibrates each counter: bytes = counter * factor."""
+    import glob
+    import subprocess
+    out_root = os.path.join(ROOT, "gpurun_out", "counters")
+    os.makedirs(out_root, exist_ok=True)
+    py = sys.executable
+
+    def prof(tag, extra, bench_args, limit):
+        d = os.path.join(out_root, tag)
+        cmd = ["timeout", "-s", "KILL", str(limit), "rocprofv3"] + extra + \
+              ["--output-format", "csv", "-d", d, "-o", "run", "--", py,
+               os.path.join(ROOT, "bench.py")] + bench_args
+        log("[collect] " + " ".join(cmd[4:]))
+        r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
+                           env=dict(os.environ, TMPDIR="/tmp"))
+        if r.returncode != 0:
+            log(r.stdout[-3000:])
+            raise SystemExit(f"rocprofv3 step {tag} failed with status {r.returncode}")
+        return d, " ".join(["rocprofv3"] + extra + ["--", "python", "bench.py"] + bench_args)
+
+    def find(d, suffix):
+        f = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+        if not f:
+            raise SystemExit(f"no {suffix} under {d}")
+        return f[0]
+
+    summary = {"kernels": {}, "commands": {}}
+    # 1. kernel trace of the headline command
+    targs = ["--steps", "20", "--warmup", "2", "--skip", "split,rtm,gradient,cpu,check"]
+    d, cmd = prof("trace_headline", ["--kernel-trace", "--stats"], targs, 300)
+    stats = find(d, "_kernel_stats.csv")
+    summary["commands"]["trace_headline"] = cmd
+    summary["trace_headline"] = {}
+    for name in ("star", "box2", "box4"):
+        ns, calls = _stats_mean_ns(stats, COUNTED[name][1])
+        summary["trace_headline"][name] = {"avg_ns": ns, "calls": calls}
+    # 2. counters per kernel, copy first (calibration)
+    n = 512
+    grid_bytes = (n + 8) * (n + 8) * (n + 8) * 4        # the padded 520^3 FP32 grid
+    factors = {}
+    for name, (src, sym, bpp) in COUNTED.items():
+        e = {"source": src, "source_sha": source_sha(src), "symbol": sym}
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            d, cmd = prof(f"{name}_{ctr}", ["--pmc", ctr], ["--only", name, "--steps", "3",
+                                                             "--warmup", "1"], 90)
+            kib, cnt = _counter_mean(find(d, "_counter_collection.csv"), sym)
+            e[ctr.lower() + "_kib"] = kib
+            summary["commands"][f"{name}_{ctr}"] = cmd
+            if name == "copy":
+                # the copy reads and writes one padded grid
+                factors[ctr] = grid_bytes / (kib * 1024.0)
+        summary["kernels"][name] = e
+    summary["factors"] = factors
+    for name, e in summary["kernels"].items():
+        fb = e["fetch_size_kib"] * 1024.0 * factors["FETCH_SIZE"]
+        wb = e["write_size_kib"] * 1024.0 * factors["WRITE_SIZE"]
+        e["fetch_bytes"], e["write_bytes"] = fb, wb
+        e["hbm_bytes_per_launch"] = fb + wb
+        e["algorithmic_bytes_per_launch"] = COUNTED[name][2] * n ** 3 if name != "copy" \
+            else 2.0 * grid_bytes
+        e["traffic_over_algorithmic"] = (fb + wb) / e["algorithmic_bytes_per_launch"]
+    os.makedirs(PROFILES, exist_ok=True)
+    json.dump(summary, open(COUNTERS_JSON, "w"), indent=1)
+    lines = ["# rocprofv3 summaries behind bench.py's roofline (512^3 headline grid)",
+             "# produced by: python bench.py --collect  (runs the commands below as children)",
+             ""]
+    lines.append("## kernel trace (--kernel-trace --stats) of the headline command")
+    lines.append("command: " + summary["commands"]["trace_headline"])
+    for k, v in summary["trace_headline"].items():
+        lines.append(f"  {k:6s} {COUNTED[k][1]:28s} calls {v['calls']:4d}  avg "
+                     f"{(v['avg_ns'] or 0) / 1e3:9.2f} us")
+    lines.append("")
+    lines.append("## HBM counters (per dispatch; KiB as read, bytes after copy calibration)")
+    lines.append(f"calibration: plain copy of one {n + 8}^3 FP32 grid ({grid_bytes} B each way): "
+                 f"FETCH factor {factors['FETCH_SIZE']:.4f}, WRITE factor "
+                 f"{factors['WRITE_SIZE']:.4f}")
+    for name, e in summary["kernels"].items():
+        lines.append(f"  {name:12s} FETCH {e['fetch_size_kib']:12.1f} KiB  WRITE "
+                     f"{e['write_size_kib']:12.1f} KiB  -> {e['hbm_bytes_per_launch'] / 1e6:9.1f} MB"
+                     f"  ({e['traffic_over_algorithmic']:.3f} x algorithmic)  src {e['source']} "
+                     f"{e['source_sha']}")
+        lines.append(f"      commands: {summary['commands'][name + '_FETCH_SIZE']} ; "
+                     f"{summary['commands'][name + '_WRITE_SIZE']}")
+    open(os.path.join(PROFILES, "counters_512.txt"), "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def profile_only(args, torch, mms, synth, grid, x, outs, sweeps, c_box4, c_box3, dev):

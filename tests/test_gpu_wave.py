@@ -238,9 +238,10 @@ def test_checkpointing_gives_identical_gradient(mms):
 
 
 def test_gradient_vs_oracle_64(mms):
-    """Gradient of the receiver misfit w.r.t. v^2 at 64^3 against the FP64 oracle."""
+    """CPU reference gradient: the workload recipe at 64^3 (W = 8, 1000 steps, checkpoints
+    every 50), gradient of the receiver misfit w.r.t. v^2 against the FP64 oracle."""
     from paper_2507_11067_amd.autograd import misfit, propagate
-    n, nt = 64, 300
+    n, nt = 64, 1000
     s, grid, m, prob = autograd_problem(mms, n, nt, 41, K=50)
     s0 = synth.wave_setup(n, nt, seed=None, sponge_width=8, dt=s.dt)   # layers only
     ow0 = oracle.Wave.from_setup(s0, LAP)
