@@ -89,7 +89,9 @@ struct Shape {
     static constexpr int NCH = (Q * WX + 31) / 32;  // 32-wide K steps per dz
     static constexpr int NU = Q * NCH;              // Toeplitz fragment pairs
     static constexpr int LR = BYT + 2 * R;          // LDS rows of a plane
-    static constexpr int LP = BXT + 8 + 8;          // LDS row pitch, 16-bit cells (8 spare)
+    // LDS row pitch in 16-bit cells: 2*LP bytes = 16 mod 128, so the 16-byte B-fragment
+    // reads of 8 consecutive rows land on 8 distinct groups of 4 banks
+    static constexpr int LP = BXT + 8;
     static constexpr int C4 = BXT / 4 + 2;          // float4 per staged row
     static constexpr int NS = LR * C4;              // float4 per staged plane
     static constexpr int NSK = (NS + 64 * NW - 1) / (64 * NW);
@@ -228,40 +230,61 @@ __global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
     store_plane();
     if (z_first + 1 < z_last) load_plane(z_first + 1);
     __syncthreads();
-    for (int zi = z_first; zi < z_last; ++zi) {
+    // B fragments of chunk ch (hi and lo) into buffer set `buf`
+    uint4 bh[2][NT], bl[2][NT];
+    auto load_b = [&](int ch, int buf) {
+        const int k0 = 32 * ch + 8 * grp;
+        const int dyi = k0 / WX, xg = (k0 % WX) / 8;
+        const bool kval = dyi < Q;
+        // the padded tail of K reads a valid row and is masked to zero
+        const uint32_t km = kval ? 0xffffffffu : 0u;
+        const int row = wrow + n + (kval ? dyi : 0);
 #pragma unroll
-        for (int ch = 0; ch < NCH; ++ch) {
-            const int k0 = 32 * ch + 8 * grp;
-            const int dyi = k0 / WX, xg = (k0 % WX) / 8;
-            const bool kval = dyi < Q;
-            // the padded tail of K reads a valid row and is masked to zero
-            const uint32_t km = kval ? 0xffffffffu : 0u;
-            const int row = wrow + n + (kval ? dyi : 0);
-            uint4 bhi[NT], blo[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const uint4 h = *reinterpret_cast<const uint4 *>(&sm.dhi[row][16 * t + 8 * xg]);
-                bhi[t] = make_uint4(h.x & km, h.y & km, h.z & km, h.w & km);
-                if constexpr (SPLIT3) {
-                    const uint4 l = *reinterpret_cast<const uint4 *>(&sm.dlo[row][16 * t + 8 * xg]);
-                    blo[t] = make_uint4(l.x & km, l.y & km, l.z & km, l.w & km);
-                }
+        for (int t = 0; t < NT; ++t) {
+            const uint4 h = *reinterpret_cast<const uint4 *>(&sm.dhi[row][16 * t + 8 * xg]);
+            bh[buf][t] = make_uint4(h.x & km, h.y & km, h.z & km, h.w & km);
+            if constexpr (SPLIT3) {
+                const uint4 l = *reinterpret_cast<const uint4 *>(&sm.dlo[row][16 * t + 8 * xg]);
+                bl[buf][t] = make_uint4(l.x & km, l.y & km, l.z & km, l.w & km);
             }
+        }
+    };
+    // A fragments of unit u = ch * Q + (dz + R) into ring slot `slot`
+    constexpr int PF = 3;   // A-fragment ring: unit u+2 is requested while unit u computes
+    uint4 ah[PF], al[PF];
+    auto load_a = [&](int u, int slot) {
+        const int ch = u / Q, dzi = u % Q;
+        ah[slot] = sm.afrag[dzi * NCH + ch][0][lane];
+        if constexpr (SPLIT3) al[slot] = sm.afrag[dzi * NCH + ch][1][lane];
+    };
+
+    for (int zi = z_first; zi < z_last; ++zi) {
+        // software pipeline over the (chunk, dz) units of this plane: the next chunk's B
+        // fragments and the A fragments two units ahead are in flight while a unit's
+        // 3 x NT MFMAs issue
+        load_b(0, 0);
+        load_a(0, 0);
+        if (S::NU > 1) load_a(1, 1);
 #pragma unroll
-            for (int dz = -R; dz <= R; ++dz) {
-                // input plane zi feeds output zi - dz, held in acc[R - dz]
-                const uint4 ahi = sm.afrag[(dz + R) * NCH + ch][0][lane];
+        for (int u = 0; u < S::NU; ++u) {
+            const int ch = u / Q, dzi = u % Q;
+            if (dzi == 0 && ch + 1 < NCH) load_b(ch + 1, (ch + 1) & 1);
+            if (u + 2 < S::NU) load_a(u + 2, (u + 2) % PF);
+            // keep the requests above this unit's MFMAs (the scheduler would sink them)
+            __builtin_amdgcn_sched_barrier(0);
+            const uint4 &ahi = ah[u % PF];
+            // input plane zi feeds output zi - dz (dz = dzi - R), held in acc[Q - 1 - dzi]
+            floatx4 *ac = acc[Q - 1 - dzi];
+            const uint4 *bhi = bh[ch & 1];
 #pragma unroll
-                for (int t = 0; t < NT; ++t) acc[R - dz][t] = mfma<PREC>(ahi, bhi[t], acc[R - dz][t]);
-                if constexpr (SPLIT3) {
-                    const uint4 alo = sm.afrag[(dz + R) * NCH + ch][1][lane];
+            for (int t = 0; t < NT; ++t) ac[t] = mfma<PREC>(ahi, bhi[t], ac[t]);
+            if constexpr (SPLIT3) {
+                const uint4 &alo = al[u % PF];
+                const uint4 *blo = bl[ch & 1];
 #pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        acc[R - dz][t] = mfma<PREC>(ahi, blo[t], acc[R - dz][t]);
+                for (int t = 0; t < NT; ++t) ac[t] = mfma<PREC>(ahi, blo[t], ac[t]);
 #pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        acc[R - dz][t] = mfma<PREC>(alo, bhi[t], acc[R - dz][t]);
-                }
+                for (int t = 0; t < NT; ++t) ac[t] = mfma<PREC>(alo, bhi[t], ac[t]);
             }
         }
         // output plane zi - R is complete (outputs outside [zb, ze) are dropped)
