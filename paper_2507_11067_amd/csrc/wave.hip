@@ -22,6 +22,8 @@ namespace {
 
 enum { MODE_FWD = 0, MODE_ADJ = 1, MODE_ENERGY = 2 };
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
 struct WaveArgs {
     Geom g;
     float c[9];           // per-axis weights, k + r (symmetric)
@@ -285,7 +287,9 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                 }
                 if (MODE != MODE_ENERGY && live) {
                     if (x0 + 3 < g.nx) {
-                        *reinterpret_cast<float4 *>(po) = make_float4(r[0], r[1], r[2], r[3]);
+                        // streaming store: the next step reads this field from HBM anyway
+                        const f4v v = {r[0], r[1], r[2], r[3]};
+                        __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(po));
                     } else {
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
