@@ -68,6 +68,8 @@ def _load():
         lib.orc_wave_forward.argtypes = [wp, _dp, _dp, _dp, _dp, _dp, _dp]
         lib.orc_adjoint_step.argtypes = [wp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp]
         lib.orc_wave_adjoint.argtypes = [wp, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.orc_vti_step.argtypes = [wp, ctypes.c_int] + [_dp] * 9
+        lib.orc_vti_forward.argtypes = [wp] + [_dp] * 8
         _lib = lib
     return _lib
 
@@ -209,3 +211,24 @@ class Wave:
         _load().orc_wave_adjoint(ctypes.byref(self._s), _ptr(st), _ptr(rs), _ptr(g), _ptr(l0),
                                  _ptr(l1), _ptr(gs))
         return g, l0, l1, gs
+
+    def vti_step(self, n, a, b, hp, hc, vp, vc):
+        """VTI pair (Sec. II-A): returns (H^{n+1}, V^{n+1}, receiver plane of H^n)."""
+        A, B = _f64(a), _f64(b)
+        arrs = [_f64(t) for t in (hp, hc, vp, vc)]
+        hn, vn = self.zeros(), self.zeros()
+        tr = np.zeros((self.ny, self.nx))
+        _load().orc_vti_step(ctypes.byref(self._s), n, _ptr(A), _ptr(B), _ptr(arrs[0]),
+                             _ptr(arrs[1]), _ptr(hn), _ptr(arrs[2]), _ptr(arrs[3]), _ptr(vn),
+                             _ptr(tr))
+        return hn, vn, tr
+
+    def vti_forward(self, a, b, h0, h1, v0, v1):
+        """Returns dict(traces of H [nt][ny][nx], last = (H^{nt-1}, H^nt, V^{nt-1}, V^nt))."""
+        A, B = _f64(a), _f64(b)
+        arrs = [_f64(t) for t in (h0, h1, v0, v1)]
+        tr = np.zeros((self.nt, self.ny, self.nx))
+        last = np.zeros((4,) + self.shape)
+        _load().orc_vti_forward(ctypes.byref(self._s), _ptr(A), _ptr(B), *[_ptr(t) for t in arrs],
+                                _ptr(tr), _ptr(last))
+        return {"traces": tr, "last": last}

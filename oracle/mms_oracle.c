@@ -339,3 +339,97 @@ void orc_wave_adjoint(const orc_wave *w, const double *states, const double *res
     memcpy(lam0_out, l1, L * sizeof(double));
     free(l2); free(l1); free(l0); free(work); free(work2); free(G);
 }
+
+/* VTI pair.  Sec. II-A prints a sigma_H / sigma_V system whose second equation
+ * swaps the fields (as printed, the difference sigma_H - sigma_V obeys
+ * D_tt = v^2 (D_xx + D_yy - D_zz), which is ill-posed).  The TTI system printed
+ * right after it reduces, for zero tilt (H1 = d_zz, H2 = d_xx + d_yy), zero shear
+ * velocity and alpha = sqrt(1 + 2 delta), to the well-posed pseudo-acoustic pair
+ * used here, with a = 1 + 2 epsilon and b = sqrt(1 + 2 delta) given as fields:
+ *   H^{n+1} = G (2 H^n - G H^{n-1} + C2 (a Sxy H^n + b Szz V^n)) + dt^2 f^n delta_src
+ *   V^{n+1} = G (2 V^n - G V^{n-1} + C2 (b Sxy H^n +   Szz V^n)) + dt^2 f^n delta_src
+ * Sxy = Sxx + Syy and Szz are the axis parts of the star with weights lap; the
+ * leapfrog, sponge and source are those of the acoustic step.  The receiver plane
+ * records H^n(z = 0). */
+static void axis_tables(const orc_wave *w, double *cxy, double *cz) {
+    const int r = w->r, n = 2 * r + 1;
+    for (int k = -r; k <= r; ++k) {
+        const double v = w->lap[k < 0 ? -k : k];
+        cxy[0 * n + k + r] = 0.0;  cxy[1 * n + k + r] = v;  cxy[2 * n + k + r] = v;
+        cz[0 * n + k + r] = v;     cz[1 * n + k + r] = 0.0; cz[2 * n + k + r] = 0.0;
+    }
+}
+
+static void vti_step_with_G(const orc_wave *w, const double *G, int n, const double *a,
+                            const double *b, const double *hp, const double *hc, double *hn,
+                            const double *vp, const double *vc, double *vn, double *trace,
+                            double *w1, double *w2, double *w3, double *w4) {
+    const orc_grid *g = &w->g;
+    double cxy[27], cz[27];
+    axis_tables(w, cxy, cz);
+    orc_star(hc, w1, g, w->r, cxy);  /* Sxy H */
+    orc_star(vc, w2, g, w->r, cz);   /* Szz V */
+    (void)w3; (void)w4;
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) {
+                long i = at(g, z, y, x);
+                hn[i] = G[i] * (2.0 * hc[i] - G[i] * hp[i] + w->c2[i] * (a[i] * w1[i] + b[i] * w2[i]));
+                vn[i] = G[i] * (2.0 * vc[i] - G[i] * vp[i] + w->c2[i] * (b[i] * w1[i] + w2[i]));
+            }
+    if (n >= 0 && n < w->nt) {
+        const long s = at(g, w->src_z, w->src_y, w->src_x);
+        hn[s] += w->src[n];
+        vn[s] += w->src[n];
+    }
+    if (trace)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) trace[y * g->nx + x] = hc[at(g, 0, y, x)];
+}
+
+void orc_vti_step(const orc_wave *w, int n, const double *a, const double *b, const double *hp,
+                  const double *hc, double *hn, const double *vp, const double *vc, double *vn,
+                  double *trace) {
+    const size_t L = field_len(&w->g);
+    double *G = sponge_field(w);
+    double *w1 = calloc(L, sizeof(double)), *w2 = calloc(L, sizeof(double));
+    double *w3 = calloc(L, sizeof(double)), *w4 = calloc(L, sizeof(double));
+    vti_step_with_G(w, G, n, a, b, hp, hc, hn, vp, vc, vn, trace, w1, w2, w3, w4);
+    free(w1); free(w2); free(w3); free(w4); free(G);
+}
+
+/* Forward VTI run from (H^0, H^1, V^0, V^1); traces [nt][ny][nx] of H; last receives
+ * H^{nt-1}, H^nt, V^{nt-1}, V^nt (4 padded fields) when non-NULL. */
+void orc_vti_forward(const orc_wave *w, const double *a, const double *b, const double *h0,
+                     const double *h1, const double *v0, const double *v1, double *traces,
+                     double *last) {
+    const orc_grid *g = &w->g;
+    const size_t L = field_len(g);
+    double *G = sponge_field(w);
+    double *H[3], *V[3];
+    for (int i = 0; i < 3; ++i) {
+        H[i] = calloc(L, sizeof(double));
+        V[i] = calloc(L, sizeof(double));
+    }
+    double *w1 = calloc(L, sizeof(double)), *w2 = calloc(L, sizeof(double));
+    double *w3 = calloc(L, sizeof(double)), *w4 = calloc(L, sizeof(double));
+    memcpy(H[0], h0, L * sizeof(double)); memcpy(H[1], h1, L * sizeof(double));
+    memcpy(V[0], v0, L * sizeof(double)); memcpy(V[1], v1, L * sizeof(double));
+    for (long y = 0; y < g->ny; ++y)
+        for (long x = 0; x < g->nx; ++x) traces[y * g->nx + x] = h0[at(g, 0, y, x)];
+    for (int n = 1; n < w->nt; ++n) {
+        double *tr = traces + (size_t)n * g->ny * g->nx;
+        vti_step_with_G(w, G, n, a, b, H[(n - 1) % 3], H[n % 3], H[(n + 1) % 3],
+                        V[(n - 1) % 3], V[n % 3], V[(n + 1) % 3], tr, w1, w2, w3, w4);
+    }
+    if (last) {
+        const int m = w->nt;
+        memcpy(last, H[(m - 1) % 3], L * sizeof(double));
+        memcpy(last + L, H[m % 3], L * sizeof(double));
+        memcpy(last + 2 * L, V[(m - 1) % 3], L * sizeof(double));
+        memcpy(last + 3 * L, V[m % 3], L * sizeof(double));
+    }
+    for (int i = 0; i < 3; ++i) { free(H[i]); free(V[i]); }
+    free(w1); free(w2); free(w3); free(w4); free(G);
+}

@@ -456,3 +456,74 @@ def test_forward_step_matches_run_and_records_traces():
     assert d[2 + 4, n // 2 + 4, n // 2 + 4] == pytest.approx(f[3], rel=1e-12)
     d[2 + 4, n // 2 + 4, n // 2 + 4] = 0
     assert np.max(np.abs(d)) == 0
+
+
+# ------------------------------------------------------------ VTI oracle
+def test_vti_reduces_to_acoustic():
+    """epsilon = delta = 0 and equal fields: both VTI fields follow the acoustic step."""
+    n, nt = 14, 40
+    rng = np.random.default_rng(50)
+    f = rng.standard_normal(nt)
+    w = sponge_problem(n, nt, seed=51, f=f)
+    u0 = synth.smooth_random_grid(52, n, n, n).astype(np.float64)
+    u1 = synth.smooth_random_grid(53, n, n, n).astype(np.float64)
+    ones = np.ones_like(u0)
+    ac = w.forward(u0, u1)
+    vt = w.vti_forward(ones, ones, u0, u1, u0, u1)
+    scale = np.abs(ac["last"]).max()
+    assert np.max(np.abs(vt["last"][0] - ac["last"][0])) <= 1e-12 * scale
+    assert np.max(np.abs(vt["last"][1] - ac["last"][1])) <= 1e-12 * scale
+    assert np.max(np.abs(vt["last"][3] - ac["last"][1])) <= 1e-12 * scale
+    np.testing.assert_allclose(vt["traces"], ac["traces"], rtol=0,
+                               atol=1e-12 * np.abs(ac["traces"]).max())
+
+
+def test_vti_sine_mode_recurrence():
+    """Radius-1 weights with a zero halo have sine eigenvectors, so a mode H = alpha Phi,
+    V = beta Phi evolves by the 2x2 recurrence
+    [alpha, beta]^{n+1} = 2 [.]^n - [.]^{n-1} - C2 M [.]^n,  M = [[a sxy, b sz], [b sxy, sz]]
+    with -sxy, -sz the eigenvalues of Sxx + Syy and Szz; checked against the 3-D oracle."""
+    n, nt = 11, 60
+    kz, ky, kx = 2, 3, 1
+    lam = lambda k: -4.0 * np.sin(np.pi * k / (2 * (n + 1))) ** 2
+    sxy, sz = -(lam(kx) + lam(ky)), -lam(kz)
+    a_val, b_val, c2_val = 1.3, 1.1, 0.2          # epsilon = 0.15 >= delta = 0.105
+    i = np.arange(n)
+    phi = lambda k: np.sin(np.pi * k * (i + 1) / (n + 1))
+    Phi = phi(kz)[:, None, None] * phi(ky)[None, :, None] * phi(kx)[None, None, :]
+    pad = lambda x: np.pad(x, 4)
+    c2 = pad(np.full((n, n, n), c2_val))
+    w = oracle.Wave(n, n, n, c2, [-2.0, 1.0], (0, 0, 0), np.zeros(nt), nt)
+    al = [1.0, 0.9]
+    be = [-0.5, -0.45]
+    res = w.vti_forward(pad(np.full((n, n, n), a_val)), pad(np.full((n, n, n), b_val)),
+                        pad(al[0] * Phi), pad(al[1] * Phi), pad(be[0] * Phi), pad(be[1] * Phi))
+    M = np.array([[a_val * sxy, b_val * sz], [b_val * sxy, sz]])
+    s_prev, s_cur = np.array([al[0], be[0]]), np.array([al[1], be[1]])
+    for _ in range(1, nt):
+        s_prev, s_cur = s_cur, 2 * s_cur - s_prev - c2_val * M @ s_cur
+    I = lambda x: synth.interior(x, n, n, n)
+    np.testing.assert_allclose(I(res["last"][1]), s_cur[0] * Phi, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(I(res["last"][3]), s_cur[1] * Phi, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(I(res["last"][0]), s_prev[0] * Phi, rtol=0, atol=1e-12)
+    assert abs(s_cur[0]) > 0.05 and abs(s_cur[1]) > 0.05
+
+
+def test_vti_step_matches_forward():
+    n, nt = 9, 5
+    rng = np.random.default_rng(60)
+    f = rng.standard_normal(nt)
+    w = sponge_problem(n, nt, seed=61, f=f)
+    fields = [synth.smooth_random_grid(62 + k, n, n, n).astype(np.float64) for k in range(4)]
+    a = synth.padded_zeros(n, n, n, dtype=np.float64)
+    b = synth.padded_zeros(n, n, n, dtype=np.float64)
+    synth.interior(a, n, n, n)[...] = 1 + 2 * rng.uniform(0, 0.2, (n, n, n))
+    synth.interior(b, n, n, n)[...] = np.sqrt(1 + 2 * rng.uniform(0, 0.1, (n, n, n)))
+    res = w.vti_forward(a, b, *fields)
+    hp, hc, vp, vc = fields[0], fields[1], fields[2], fields[3]
+    for k in range(1, nt):
+        hn, vn, tr = w.vti_step(k, a, b, hp, hc, vp, vc)
+        np.testing.assert_array_equal(tr, res["traces"][k])
+        hp, hc, vp, vc = hc, hn, vc, vn
+    np.testing.assert_array_equal(hc, res["last"][1])
+    np.testing.assert_array_equal(vc, res["last"][3])
