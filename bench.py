@@ -14,6 +14,7 @@ Besides the headline the same JSON line carries, each measured in this run:
   * "split_mfma": the radius-4 and radius-3 boxes three ways (FP32 VALU, BF16x3
     and FP16x3S split MFMA, plus the BF16x1 error report);
   * "rtm": the 400^3, 2000-step acoustic forward model with FP64 imaging;
+  * "vti": the 400^3, 1000-step pseudo-acoustic VTI forward model (two fields);
   * "gradient": the 256^3, 1000-step adjoint gradient with checkpointing,
     with its dot-product test;
   * "roofline" of the dominant kernel and "cpu_baseline" (the FP64 oracle on
@@ -53,9 +54,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=5)
     p.add_argument("--n", type=int, default=512, help="headline grid edge")
     p.add_argument("--only", default="", help="profile one kernel: star|box2|box4|box4_bf16x3|"
-                   "box4_fp16x3s|box3_bf16x3|wave|copy")
+                   "box4_fp16x3s|box3_bf16x3|wave|vti|copy")
     p.add_argument("--skip", default="", help="comma list of extras to skip: "
-                   "split,rtm,gradient,cpu,check")
+                   "split,rtm,vti,gradient,cpu,check")
     p.add_argument("--cpu-planes", type=int, default=0, help="oracle sample depth (0 = full grid)")
     p.add_argument("--collect", action="store_true",
                    help="run rocprofv3 (kernel trace, FETCH_SIZE, WRITE_SIZE) as child processes "
@@ -221,6 +222,8 @@ def main():
     del outs
     if "rtm" not in skip:
         result["rtm"] = bench_rtm(torch, mms, synth, dev)
+    if "vti" not in skip:
+        result["vti"] = bench_vti(torch, mms, synth, dev)
     if "gradient" not in skip:
         result["gradient"] = bench_gradient(torch, mms, synth, dev)
     if "cpu" not in skip:
@@ -308,6 +311,49 @@ def bench_rtm(torch, mms, synth, dev, n=400, nt=2000):
         if with_image:
             res["trace_max_abs"] = float(traces.abs().max().item())
             res["image_sum"] = float(image.sum().item())
+    return res
+
+
+def vti_problem(torch, mms, synth, dev, n, nt, seed=9):
+    """400^3 layered VTI medium: C2 at Courant 0.4 / sqrt(1 + 2 eps_max), Thomsen fields."""
+    s = synth.wave_setup(n, nt, seed=seed, sponge_width=32)
+    grid = mms.Grid(n, n, n)
+    eps, delta = synth.thomsen_fields(n, n, n, seed + 1, sy=grid.sy)
+    shrink = 1.0 / (1.0 + 2.0 * float(eps.max()))
+    a = torch.from_numpy(1 + 2 * eps).to(dev)
+    b = torch.from_numpy(np.sqrt(1 + 2 * delta).astype(np.float32)).to(dev)
+    c2 = torch.from_numpy(s.c2).to(dev)
+    f = torch.from_numpy(s.src_dt2f).to(dev)
+    return s, grid, a, b, c2, f, shrink
+
+
+def bench_vti(torch, mms, synth, dev, n=400, nt=1000):
+    """Pseudo-acoustic VTI forward model, 400^3, 1000 steps, H traces recorded."""
+    log(f"[bench] vti setup {n}^3 x {nt}")
+    s, grid, a, b, c2, f, shrink = vti_problem(torch, mms, synth, dev, n, nt)
+    traces = torch.zeros((nt, n, n), device=dev)
+    w = mms.Wave(grid, c2, LAP, nt, shrink, s.sponge_width, s.sponge_alpha, s.sponge_faces,
+                 s.src, f, traces)
+    H = [grid.zeros(dev) for _ in range(2)]
+    V = [grid.zeros(dev) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    w.record(0, H[0])
+    for k in range(1, nt):
+        w.vti_step(k, a, b, H[(k - 1) % 2], H[k % 2], H[(k + 1) % 2],
+                   V[(k - 1) % 2], V[k % 2], V[(k + 1) % 2])
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    gpts = grid.points * (nt - 1) / (ms * 1e-3) / 1e9
+    bpp = 36.0      # reads H, V at n and n-1, C2, a, b; writes H, V
+    res = {"grid": [n, n, n], "steps": nt - 1, "ms_total": ms, "ms_per_step": ms / (nt - 1),
+           "gpoints_s": gpts, "gbs": gpts * bpp, "hbm_frac": gpts * bpp / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_point": bpp,
+           "trace_max_abs": float(traces.abs().max().item()),
+           "finite": bool(torch.isfinite(H[nt % 2]).all().item())}
+    log(f"[bench] vti: {gpts:.1f} Gpoints/s ({ms:.0f} ms, {gpts * bpp:.0f} GB/s)")
     return res
 
 
@@ -497,8 +543,9 @@ COUNTED = {
     "box4_bf16x3": ("box_mfma.hip", "box_mfma_kernel<4, 1>", 8.0),
     "box3_bf16x3": ("box_mfma.hip", "box_mfma_kernel<3, 1>", 8.0),
     "wave": ("wave.hip", "wave_kernel<4, 0, false", 16.0),   # 400^3 forward step, no image
+    "vti": ("vti.hip", "vti_kernel<4", 36.0),                # 400^3 VTI step
 }
-COUNTED_POINTS = {"wave": 400 ** 3}
+COUNTED_POINTS = {"wave": 400 ** 3, "vti": 400 ** 3}
 
 
 def source_sha(fname):
@@ -640,6 +687,20 @@ def profile_only(args, torch, mms, synth, grid, x, outs, sweeps, c_box4, c_box3,
         f = lambda: mms.stencil_apply(x, out, grid, "box", r, c, precision=prec)
     elif k == "copy":
         f = lambda: out.copy_(x)
+    elif k == "vti":
+        n = 400
+        s, g4, ta, tb, c2, fsrc, shrink = vti_problem(torch, mms, synth, dev, n, 64)
+        w = mms.Wave(g4, c2, LAP, 64, shrink, s.sponge_width, s.sponge_alpha, s.sponge_faces,
+                     s.src, fsrc, None, None)
+        H = [g4.zeros(dev) for _ in range(2)]
+        V = [g4.zeros(dev) for _ in range(2)]
+        it = [0]
+
+        def f():
+            i = it[0] % 60 + 1
+            w.vti_step(i, ta, tb, H[(i - 1) % 2], H[i % 2], H[(i + 1) % 2],
+                       V[(i - 1) % 2], V[i % 2], V[(i + 1) % 2])
+            it[0] += 1
     elif k == "wave":
         n = 400
         s = synth.wave_setup(n, 64, seed=7, sponge_width=32)

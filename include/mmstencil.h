@@ -157,6 +157,23 @@ int mms_wave_adjoint(const mms_wave *w, int n_hi, int n_lo, float *const *lams,
                      const float *const *us, const float *resid, double *grad, void *stream);
 
 /*
+ * mms_vti_step -- one step n (1 <= n < nt) of the pseudo-acoustic VTI pair that RTM
+ * in VTI media runs (Sec. II-A).  The paper prints a sigma_H / sigma_V system whose
+ * second equation, as printed, is ill-posed; the TTI system printed next to it
+ * reduces, for zero tilt, zero shear velocity and alpha = sqrt(1 + 2 delta), to
+ *   H^{n+1} = G (2 H^n - G H^{n-1} + C2 (a Sxy H^n + b Szz V^n)) + src_dt2f[n] delta_src
+ *   V^{n+1} = G (2 V^n - G V^{n-1} + C2 (b Sxy H^n +   Szz V^n)) + src_dt2f[n] delta_src
+ * which is what this computes.  a = 1 + 2 epsilon, b = sqrt(1 + 2 delta): device grids
+ * (layout g).  Sxy = Sxx + Syy and Szz are the axis parts of the star with weights
+ * w->lap; C2, G, the source and dt as in mms_wave_step; traces[n] = H^n(z = 0); the
+ * image is not used.  h_next may equal h_prev and v_next may equal v_prev; neither may
+ * overlap h_cur or v_cur.
+ */
+int mms_vti_step(const mms_wave *w, int n, const float *a, const float *b, const float *h_prev,
+                 const float *h_cur, float *h_next, const float *v_prev, const float *v_cur,
+                 float *v_next, void *stream);
+
+/*
  * mms_wave_energy -- FP64 discrete energy of the leapfrog scheme without
  * sponge or source, E^{n+1/2} = sum (u^{n+1}-u^n)^2 / C2 - <u^{n+1}, S u^n>,
  * which the scheme conserves exactly for a symmetric S.  *out_dev (device) is

@@ -195,6 +195,15 @@ class Wave:
             _dev_ptr(resid, "resid", torch.float32, self.nt * g.ny * g.nx),
             _dev_ptr(grad, "grad", torch.float64, g.points), _stream(stream)), "mms_wave_adjoint")
 
+    def vti_step(self, n, a, b, h_prev, h_cur, h_next, v_prev, v_cur, v_next, stream=None):
+        """One pseudo-acoustic VTI step (see mms_vti_step); a = 1 + 2 eps, b = sqrt(1 + 2 delta)."""
+        g = self.grid
+        check(lib().mms_vti_step(ctypes.byref(self._w), int(n), _grid_ptr(a, g, "a"),
+                                 _grid_ptr(b, g, "b"), _grid_ptr(h_prev, g, "h_prev"),
+                                 _grid_ptr(h_cur, g, "h_cur"), _grid_ptr(h_next, g, "h_next"),
+                                 _grid_ptr(v_prev, g, "v_prev"), _grid_ptr(v_cur, g, "v_cur"),
+                                 _grid_ptr(v_next, g, "v_next"), _stream(stream)), "mms_vti_step")
+
     def energy(self, u_n, u_np1, stream=None) -> float:
         out = torch.zeros(1, dtype=torch.float64, device=u_n.device)
         check(lib().mms_wave_energy(ctypes.byref(self._w), _grid_ptr(u_n, self.grid, "u_n"),

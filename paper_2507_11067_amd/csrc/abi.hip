@@ -18,6 +18,9 @@ int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *o
                 int64_t npartials, hipStream_t s);
 int64_t wave_energy_blocks(const mms_wave *w);
 int dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, hipStream_t s);
+int vti_step(const mms_wave *w, int n, const float *fa, const float *fb, const float *hp,
+             const float *hc, float *hn, const float *vp, const float *vc, float *vn,
+             hipStream_t s);
 int reduce_grid_dot(const float *a, const float *b, const mms_grid *g, double *out, double *part,
                     hipStream_t s);
 int reduce_flat(const float *a, const float *b, float *resid, int64_t n, int misfit, double *out,
@@ -156,6 +159,29 @@ int mms_wave_step(const mms_wave *w, int n, const float *u_prev, const float *u_
     if (u_prev != u_next && overlap(u_prev, bytes, u_next, bytes)) return MMS_EINVAL;
     if (grid_empty(&w->g)) return MMS_OK;
     return wave_step(w, n, u_prev, u_cur, u_next, (hipStream_t)stream);
+}
+
+int mms_vti_step(const mms_wave *w, int n, const float *a, const float *b, const float *h_prev,
+                 const float *h_cur, float *h_next, const float *v_prev, const float *v_cur,
+                 float *v_next, void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    const float *ins[] = {a, b, h_prev, h_cur, v_prev, v_cur};
+    for (const float *p : ins)
+        if (!p || !aligned16(p)) return MMS_EINVAL;
+    if (!h_next || !v_next || !aligned16(h_next) || !aligned16(v_next)) return MMS_EINVAL;
+    if (n < 1 || n >= w->nt) return MMS_EINVAL;
+    const int64_t bytes = grid_elems(&w->g) * (int64_t)sizeof(float);
+    const float *cur[] = {h_cur, v_cur, a, b, w->c2};
+    for (const float *p : cur)
+        if (overlap(p, bytes, h_next, bytes) || overlap(p, bytes, v_next, bytes)) return MMS_EINVAL;
+    if (overlap(h_next, bytes, v_next, bytes)) return MMS_EINVAL;
+    if (h_prev != h_next && overlap(h_prev, bytes, h_next, bytes)) return MMS_EINVAL;
+    if (v_prev != v_next && overlap(v_prev, bytes, v_next, bytes)) return MMS_EINVAL;
+    if (overlap(h_prev, bytes, v_next, bytes) || overlap(v_prev, bytes, h_next, bytes))
+        return MMS_EINVAL;
+    if (grid_empty(&w->g)) return MMS_OK;
+    return vti_step(w, n, a, b, h_prev, h_cur, h_next, v_prev, v_cur, v_next,
+                    (hipStream_t)stream);
 }
 
 int mms_wave_record(const mms_wave *w, int n, const float *u, void *stream) {

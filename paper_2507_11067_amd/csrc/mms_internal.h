@@ -62,6 +62,20 @@ __device__ __forceinline__ float4 guarded_load(const float *p, bool ok, const fl
     return ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// Absorbing sponge: g(d) = exp(-(a (W - d))^2) for a cell at distance d < W from a
+// damped face, 1 elsewhere; gaxis is the factor of one axis at interior index i of n.
+__device__ __forceinline__ float mms_g1(int d, int W, float a) {
+    if (d >= W) return 1.0f;
+    const float t = a * (float)(W - d);
+    return __expf(-t * t);
+}
+__device__ __forceinline__ float gaxis(int i, int n, int W, float a, bool lo, bool hi) {
+    float f = 1.0f;
+    if (lo) f *= mms_g1(i, W, a);
+    if (hi) f *= mms_g1(n - 1 - i, W, a);
+    return f;
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs of the MI355X (block b runs
 // on XCD b % 8).  This bijection gives every XCD one contiguous range of
 // logical tiles, so tiles that share halo cells share one L2.

@@ -44,19 +44,6 @@ struct WaveArgs {
     int faces;
 };
 
-__device__ __forceinline__ float g1(int d, int W, float a) {
-    if (d >= W) return 1.0f;
-    const float t = a * (float)(W - d);
-    return __expf(-t * t);
-}
-// damping factor of one axis at interior index i of n
-__device__ __forceinline__ float gaxis(int i, int n, int W, float a, bool lo, bool hi) {
-    float f = 1.0f;
-    if (lo) f *= g1(i, W, a);
-    if (hi) f *= g1(n - 1 - i, W, a);
-    return f;
-}
-
 template <int R, int MODE, bool GRAD, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     constexpr int NF = (MODE == MODE_ADJ && GRAD) ? 2 : 1;  // stencil fields

@@ -164,3 +164,23 @@ def smooth_random_grid(seed: int, nx: int, ny: int, nz: int, sigma: float = 2.0)
     a = padded_zeros(nx, ny, nz)
     interior(a, nx, ny, nz)[...] = p.astype(np.float32)
     return a
+
+
+def thomsen_fields(nx: int, ny: int, nz: int, seed: int, sy: int | None = None):
+    """Padded FP32 Thomsen parameters (epsilon, delta) of a layered VTI medium:
+    five depth layers with epsilon in [0.05, 0.25] and delta in [0, 0.12],
+    delta <= epsilon, each with a smooth +-10% perturbation; zero halo."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    bounds = np.sort(rng.uniform(0.1, 0.9, 4)) * nz
+    layer = np.searchsorted(bounds, np.arange(nz) + 0.5)
+    eps_l = rng.uniform(0.05, 0.25, 5)
+    del_l = np.minimum(rng.uniform(0.0, 0.12, 5), eps_l)
+    noise = gaussian_filter(rng.standard_normal((nz, ny, nx)), sigma=4.0, mode="reflect")
+    noise *= 0.1 / max(np.abs(noise).max(), 1e-30)
+    out = []
+    for vals in (eps_l, del_l):
+        a = padded_zeros(nx, ny, nz, sy=sy)
+        interior(a, nx, ny, nz)[...] = (vals[layer][:, None, None] * (1 + noise)).astype(np.float32)
+        out.append(a)
+    return out[0], out[1]
