@@ -43,6 +43,28 @@ inline int pick_zchunk(int nz, int64_t cols, int64_t slots, int zmin, int zmax) 
     return (int)zc;
 }
 
+// z-chunk that minimises the modelled time of a launch whose blocks all take about
+// the same time: ceil(blocks / slots) rounds of (zchunk + overhead) planes, where
+// overhead is the per-block fill of the z pipeline in planes, plus a quarter block
+// for the uneven finish of the last round.  Larger chunks win ties.
+inline int pick_zchunk_rounds(int nz, int64_t cols, int64_t slots, int zmin, int zmax,
+                              int overhead) {
+    if (cols < 1) cols = 1;
+    if (zmax > nz) zmax = nz > zmin ? nz : zmin;
+    int best = zmax;
+    int64_t best_cost = -1;
+    for (int zc = zmax; zc >= zmin; --zc) {
+        const int64_t nzc = (nz + zc - 1) / zc;
+        const int64_t rounds = (cols * nzc + slots - 1) / slots;
+        const int64_t cost4 = 4 * rounds * (int64_t)(zc + overhead) + zc;  // quarter planes
+        if (best_cost < 0 || cost4 < best_cost) {
+            best_cost = cost4;
+            best = zc;
+        }
+    }
+    return best;
+}
+
 // Sweep launchers (host), one per kernel family.  coeffs is a host array.
 int launch_star(const float *in, float *out, const mms_grid *g, int r, const float *coeffs,
                 hipStream_t s);

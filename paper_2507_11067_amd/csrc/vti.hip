@@ -251,7 +251,9 @@ int vti_step(const mms_wave *w, int n, const float *fa, const float *fb, const f
     g.sz = gd->sz;
     g.ntx = (g.nx + 4 * VTX - 1) / (4 * VTX);
     g.nty = (g.ny + VTY - 1) / VTY;
-    g.zchunk = pick_zchunk(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128);
+    // one 512-thread block per CU (VGPR-bound), 256 CUs; the V queue fill costs
+    // about one plane of traffic
+    g.zchunk = pick_zchunk_rounds(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128, 1);
     g.nzc = (g.nz + g.zchunk - 1) / g.zchunk;
     const int r = w->radius;
     for (int k = -r; k <= r; ++k) a.c[k + r] = w->lap[k < 0 ? -k : k];

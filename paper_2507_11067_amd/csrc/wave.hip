@@ -395,7 +395,13 @@ void fill_geom(Geom &g, const mms_grid *gd) {
     g.sz = gd->sz;
     g.ntx = (g.nx + 4 * TX - 1) / (4 * TX);
     g.nty = (g.ny + TY - 1) / TY;
-    g.zchunk = pick_zchunk(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128);
+    // one block per CU (LDS-bound).  The two-field adjoint fills two rings per
+    // block, so its chunk count follows the round model; the one-field kernels
+    // split the columns evenly over the CUs.
+    if (Cfg<MODE, GRAD>::TWO)
+        g.zchunk = pick_zchunk_rounds(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128, 10);
+    else
+        g.zchunk = pick_zchunk(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128);
     g.nzc = (g.nz + g.zchunk - 1) / g.zchunk;
 }
 
