@@ -193,6 +193,9 @@ def main():
     roof["kernel"] = {"star": "star_kernel<4>", "box2": "box_valu_kernel<2>",
                       "box4": "box_valu_kernel<4>"}[dom]
     roof["traffic"] = traffic_for(dom)
+    u = util_for(dom)
+    if u:
+        roof["rocprof"] = u
     rooflines = {}
     for name, (bound, bytes_pt, flop_pt) in per.items():
         k = kernels[name]
@@ -265,6 +268,13 @@ def bench_split(torch, mms, synth, grid, x, x_np, n, c_box4, c_box3, dev, check)
                 e["mfma_issued_tflops"] = issued
                 e["mfma_frac"] = issued / MFMA_BF16_PEAK_TF
                 e["algorithmic_tflops"] = gpts * flop / 1e3
+            u = util_for(f"box{r}_{prec}") if prec != "fp32" else None
+            if u:
+                e["rocprof_mfma_util_pct"] = u.get("MfmaUtil")
+                mops = u.get("SQ_INSTS_VALU_MFMA_MOPS_BF16")
+                if mops:
+                    e["rocprof_mfma_tflops"] = mops * 512 / (ms * 1e-3) / 1e12
+                e["rocprof_lds_bank_conflict_pct"] = u.get("LDSBankConflict")
             if check:
                 o = out.cpu().numpy()
                 got = o[sel[:, 0] + 4, sel[:, 1] + 4, sel[:, 2] + 4]
@@ -569,6 +579,36 @@ def traffic_for(name):
     return e["hbm_bytes_per_launch"]
 
 
+# utilisation passes (one rocprofv3 run each; derived counters computed by rocprofv3)
+UTIL_PASSES = {
+    "box4_bf16x3": "MfmaUtil SQ_INSTS_VALU_MFMA_MOPS_BF16 LDSBankConflict",
+    "box3_bf16x3": "MfmaUtil SQ_INSTS_VALU_MFMA_MOPS_BF16 LDSBankConflict",
+    "box4": "VALUBusy SQ_INSTS_VALU_FMA_F32 LDSBankConflict",
+    "star": "VALUBusy LDSBankConflict",
+}
+
+
+def util_for(name):
+    """Utilisation counters of one kernel from the committed summary (None if stale)."""
+    try:
+        d = json.load(open(COUNTERS_JSON))
+    except (OSError, ValueError):
+        return None
+    e = d.get("util", {}).get(name)
+    if not e or e.get("source_sha") != source_sha(COUNTED[name][0]):
+        return None
+    return {k: v for k, v in e.items() if k not in ("source", "source_sha", "command")}
+
+
+def _counter_means(csv_path, substr):
+    import csv
+    acc = {}
+    for r in csv.DictReader(open(csv_path)):
+        if substr in r["Kernel_Name"]:
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
 def _counter_mean(csv_path, substr):
     import csv
     vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
@@ -623,6 +663,14 @@ def collect_counters(args):
     for name in ("star", "box2", "box4"):
         ns, calls = _stats_mean_ns(stats, COUNTED[name][1])
         summary["trace_headline"][name] = {"avg_ns": ns, "calls": calls}
+    # 1b. kernel traces of the single-kernel commands (split MFMA boxes, wave, VTI)
+    summary["trace_only"] = {}
+    for name in ("box4_bf16x3", "box3_bf16x3", "wave", "vti"):
+        d, cmd = prof(f"trace_{name}", ["--kernel-trace", "--stats"],
+                      ["--only", name, "--steps", "20", "--warmup", "2"], 120)
+        ns, calls = _stats_mean_ns(find(d, "_kernel_stats.csv"), COUNTED[name][1])
+        summary["trace_only"][name] = {"avg_ns": ns, "calls": calls, "command": cmd,
+                                       "source_sha": source_sha(COUNTED[name][0])}
     # 2. counters per kernel, copy first (calibration)
     n = 512
     grid_bytes = (n + 8) * (n + 8) * (n + 8) * 4        # the padded 520^3 FP32 grid
@@ -640,6 +688,15 @@ def collect_counters(args):
                 factors[ctr] = grid_bytes / (kib * 1024.0)
         summary["kernels"][name] = e
     summary["factors"] = factors
+    # 3. utilisation counters
+    summary["util"] = {}
+    for name, ctrs in UTIL_PASSES.items():
+        src, sym, _ = COUNTED[name]
+        d, cmd = prof(f"{name}_util", ["--pmc"] + ctrs.split(),
+                      ["--only", name, "--steps", "3", "--warmup", "1"], 90)
+        e = {"source": src, "source_sha": source_sha(src), "command": cmd}
+        e.update(_counter_means(find(d, "_counter_collection.csv"), sym))
+        summary["util"][name] = e
     for name, e in summary["kernels"].items():
         fb = e["fetch_size_kib"] * 1024.0 * factors["FETCH_SIZE"]
         wb = e["write_size_kib"] * 1024.0 * factors["WRITE_SIZE"]
@@ -659,6 +716,11 @@ def collect_counters(args):
         lines.append(f"  {k:6s} {COUNTED[k][1]:28s} calls {v['calls']:4d}  avg "
                      f"{(v['avg_ns'] or 0) / 1e3:9.2f} us")
     lines.append("")
+    lines.append("## kernel traces (--kernel-trace --stats) of single-kernel commands")
+    for k, v in summary["trace_only"].items():
+        lines.append(f"  {k:12s} {COUNTED[k][1]:28s} calls {v['calls']:4d}  avg "
+                     f"{(v['avg_ns'] or 0) / 1e3:9.2f} us   command: {v['command']}")
+    lines.append("")
     lines.append("## HBM counters (per dispatch; KiB as read, bytes after copy calibration)")
     lines.append(f"calibration: plain copy of one {n + 8}^3 FP32 grid ({grid_bytes} B each way): "
                  f"FETCH factor {factors['FETCH_SIZE']:.4f}, WRITE factor "
@@ -670,6 +732,13 @@ def collect_counters(args):
                      f"{e['source_sha']}")
         lines.append(f"      commands: {summary['commands'][name + '_FETCH_SIZE']} ; "
                      f"{summary['commands'][name + '_WRITE_SIZE']}")
+    lines.append("")
+    lines.append("## utilisation counters (per dispatch, derived ones as computed by rocprofv3)")
+    for name, e in summary["util"].items():
+        vals = "  ".join(f"{k} {v:.4g}" for k, v in e.items()
+                         if k not in ("source", "source_sha", "command"))
+        lines.append(f"  {name:12s} {vals}  src {e['source']} {e['source_sha']}")
+        lines.append(f"      command: {e['command']}")
     open(os.path.join(PROFILES, "counters_512.txt"), "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
