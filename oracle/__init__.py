@@ -62,6 +62,10 @@ def _load():
         lp = ctypes.POINTER(ctypes.c_long)
         lib.orc_star_at.argtypes = [_dp, gp, ctypes.c_int, _dp, ctypes.c_long, lp, _dp]
         lib.orc_box_at.argtypes = [_dp, gp, ctypes.c_int, _dp, ctypes.c_long, lp, _dp]
+        for nm in ("orc_star2d", "orc_box2d"):
+            getattr(lib, nm).argtypes = [_dp, _dp, gp, ctypes.c_int, _dp]
+        for nm in ("orc_star2d_at", "orc_box2d_at"):
+            getattr(lib, nm).argtypes = [_dp, gp, ctypes.c_int, _dp, ctypes.c_long, lp, _dp]
         lib.orc_sponge_1d.argtypes = [ctypes.c_long, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, _dp]
         lib.orc_wave_step.argtypes = [wp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
@@ -114,6 +118,29 @@ def box(inp: np.ndarray, nx: int, ny: int, nz: int, radius: int, coeffs,
     return out
 
 
+def star2d(inp: np.ndarray, nx: int, ny: int, nz: int, radius: int, coeffs,
+           halo: int = 4) -> np.ndarray:
+    """2-D star on every z-plane (Table I 2DStar); coeffs [2][2r+1] (axis y, x)."""
+    a = _f64(inp)
+    out = np.zeros_like(a)
+    c = _f64(np.asarray(coeffs).reshape(2, 2 * radius + 1))
+    _load().orc_star2d(_ptr(a), _ptr(out), ctypes.byref(_grid(a, nx, ny, nz, halo)), radius,
+                       _ptr(c))
+    return out
+
+
+def box2d(inp: np.ndarray, nx: int, ny: int, nz: int, radius: int, coeffs,
+          halo: int = 4) -> np.ndarray:
+    """2-D box on every z-plane (Table I 2DBox); coeffs [dy][dx]."""
+    a = _f64(inp)
+    out = np.zeros_like(a)
+    n = 2 * radius + 1
+    c = _f64(np.asarray(coeffs).reshape(n, n))
+    _load().orc_box2d(_ptr(a), _ptr(out), ctypes.byref(_grid(a, nx, ny, nz, halo)), radius,
+                      _ptr(c))
+    return out
+
+
 def _at(fn, inp, nx, ny, nz, radius, coeffs, points, halo, shape):
     a = inp if (inp.dtype == np.float64 and inp.flags.c_contiguous) else None
     if a is None:
@@ -144,6 +171,16 @@ def sponge_1d(n: int, width: int, alpha: float, damp_lo: bool, damp_hi: bool) ->
     g = np.zeros(n, dtype=np.float64)
     _load().orc_sponge_1d(n, width, alpha, int(damp_lo), int(damp_hi), _ptr(g))
     return g
+
+
+def star2d_at(inp, nx, ny, nz, radius, coeffs, points, halo=4):
+    return _at(_load().orc_star2d_at, inp, nx, ny, nz, radius, coeffs, points, halo,
+               (2, 2 * radius + 1))
+
+
+def box2d_at(inp, nx, ny, nz, radius, coeffs, points, halo=4):
+    n = 2 * radius + 1
+    return _at(_load().orc_box2d_at, inp, nx, ny, nz, radius, coeffs, points, halo, (n, n))
 
 
 class Wave:

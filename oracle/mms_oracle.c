@@ -16,7 +16,8 @@
  * Passages followed:
  *  - star and box stencils: the problem statement of Sec. I (star reaches
  *    neighbours along the axes only, box reaches the whole (2r+1)^d cube) and
- *    the radius-4 / 8th-order high-order case of Sec. II-A;
+ *    the radius-4 / 8th-order high-order case of Sec. II-A; the 2-D kernels of
+ *    Table I (2DStar, 2DBox) applied to every z-plane of a stack of planes;
  *  - the acoustic time step: the second-order-in-time wave update that RTM
  *    (Sec. II-A, Sec. V-F) is built on, u^{n+1} = 2u^n - u^{n-1} + v^2 dt^2 L u^n
  *    + source, with the damping sponge, source and receiver reading listed in
@@ -107,6 +108,58 @@ void orc_box_at(const double *in, const orc_grid *g, int r, const double *c, lon
                          in[at(g, z + dz, y + dy, x + dx)];
         out[i] = s;
     }
+}
+
+/* 2-D star on every z-plane of the stack (Table I, 2DStarR2 / 2DStarR4):
+ * out(z, y, x) = sum_{k=-r..r} cy[k+r] in(z, y+k, x) + sum_{k=-r..r} cx[k+r] in(z, y, x+k)
+ * c is [2][2r+1]: axis y, then x.  No z neighbour is read. */
+static double star2d_at(const double *in, const orc_grid *g, int r, const double *c, long z,
+                        long y, long x) {
+    const int w = 2 * r + 1;
+    const double *cy = c, *cx = c + w;
+    double s = 0.0;
+    for (int k = -r; k <= r; ++k) s += cy[k + r] * in[at(g, z, y + k, x)];
+    for (int k = -r; k <= r; ++k) s += cx[k + r] * in[at(g, z, y, x + k)];
+    return s;
+}
+
+/* 2-D box on every z-plane (Table I, 2DBoxR2 / 2DBoxR3):
+ * out(z, y, x) = sum_{dy,dx in [-r,r]} c[dy+r][dx+r] in(z, y+dy, x+dx) */
+static double box2d_at(const double *in, const orc_grid *g, int r, const double *c, long z,
+                       long y, long x) {
+    const int w = 2 * r + 1;
+    double s = 0.0;
+    for (int dy = -r; dy <= r; ++dy)
+        for (int dx = -r; dx <= r; ++dx) s += c[(dy + r) * w + (dx + r)] * in[at(g, z, y + dy, x + dx)];
+    return s;
+}
+
+void orc_star2d(const double *in, double *out, const orc_grid *g, int r, const double *c) {
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) out[at(g, z, y, x)] = star2d_at(in, g, r, c, z, y, x);
+}
+
+void orc_box2d(const double *in, double *out, const orc_grid *g, int r, const double *c) {
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) out[at(g, z, y, x)] = box2d_at(in, g, r, c, z, y, x);
+}
+
+void orc_star2d_at(const double *in, const orc_grid *g, int r, const double *c, long npts,
+                   const long *pts, double *out) {
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < npts; ++i)
+        out[i] = star2d_at(in, g, r, c, pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
+}
+
+void orc_box2d_at(const double *in, const orc_grid *g, int r, const double *c, long npts,
+                  const long *pts, double *out) {
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < npts; ++i)
+        out[i] = box2d_at(in, g, r, c, pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]);
 }
 
 /* Transpose of the star operator on the interior (zero outside it):

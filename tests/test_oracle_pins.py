@@ -98,6 +98,27 @@ def test_point_counts_match_table1(row):
     assert int(np.count_nonzero(acc)) == pts
 
 
+@pytest.mark.parametrize("row", [r for r in read_table1() if r[1] == 2], ids=lambda r: r[0])
+def test_point_counts_match_table1_2d(row):
+    """2-D kernels act on each plane of a stack: the impulse response stays in the
+    impulse's plane and touches exactly the Table I point count there."""
+    _, _, shape, r, pts = row
+    n = 2 * r + 3
+    rng = np.random.default_rng(6)
+    acc = np.zeros((n, n, n))
+    for trial in range(2):
+        if shape == "star":
+            c = rng.uniform(0.5, 1.5, (2, 2 * r + 1))
+        else:
+            c = rng.uniform(0.5, 1.5, (2 * r + 1,) * 2)
+        delta = synth.padded_zeros(n, n, n, dtype=np.float64)
+        synth.interior(delta, n, n, n)[n // 2, n // 2, n // 2] = 1.0
+        f = oracle.star2d if shape == "star" else oracle.box2d
+        acc += np.abs(synth.interior(f(delta, n, n, n, r, c), n, n, n))
+    assert int(np.count_nonzero(acc)) == pts
+    assert int(np.count_nonzero(acc[n // 2])) == pts
+
+
 # ------------------------------------------------------------- star oracle
 def poly_field(deg_max, seed, n=12, halo=4, pure_x_degree=None):
     """Random polynomial of total degree <= deg_max on the padded grid incl. halo,
@@ -216,6 +237,44 @@ def test_star_matches_scipy_correlate1d(r):
            + ndimage.correlate1d(full, c[2], axis=2, mode="constant"))
     np.testing.assert_allclose(synth.interior(out, nx, ny, nz),
                                ref[4:4 + nz, 4:4 + ny, 4:4 + nx], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_star2d_matches_scipy_correlate1d(r):
+    nx, ny, nz = 13, 10, 3
+    rng = np.random.default_rng(30 + r)
+    a = synth.padded_zeros(nx, ny, nz, dtype=np.float64)
+    a[...] = rng.uniform(-1, 1, a.shape)  # non-zero halo, also in z: never read
+    c = rng.uniform(-1, 1, (2, 2 * r + 1))
+    out = oracle.star2d(a, nx, ny, nz, r, c)
+    full = a[:, :, :nx + 8]
+    ref = (ndimage.correlate1d(full, c[0], axis=1, mode="constant")
+           + ndimage.correlate1d(full, c[1], axis=2, mode="constant"))
+    np.testing.assert_allclose(synth.interior(out, nx, ny, nz),
+                               ref[4:4 + nz, 4:4 + ny, 4:4 + nx], rtol=0, atol=1e-13)
+    # the same as the (pinned) 3-D star whose z weights are zero
+    c3 = np.stack([np.zeros(2 * r + 1), c[0], c[1]])
+    np.testing.assert_allclose(out, oracle.star(a, nx, ny, nz, r, c3), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_box2d_matches_scipy_correlate(r):
+    nx, ny, nz = 12, 9, 3
+    rng = np.random.default_rng(40 + r)
+    a = synth.padded_zeros(nx, ny, nz, dtype=np.float64)
+    a[...] = rng.uniform(-1, 1, a.shape)
+    c = rng.uniform(-1, 1, (2 * r + 1,) * 2)  # no symmetry: a transposed axis fails
+    out = oracle.box2d(a, nx, ny, nz, r, c)
+    ref = ndimage.correlate(a[:, :, :nx + 8], c[None], mode="constant")
+    np.testing.assert_allclose(synth.interior(out, nx, ny, nz),
+                               ref[4:4 + nz, 4:4 + ny, 4:4 + nx], rtol=0, atol=1e-12)
+    idx = np.array([[0, 0, 0], [nz - 1, ny - 1, nx - 1], [1, 4, 7]])
+    np.testing.assert_allclose(oracle.box2d_at(a, nx, ny, nz, r, c, idx),
+                               synth.interior(out, nx, ny, nz)[idx[:, 0], idx[:, 1], idx[:, 2]],
+                               rtol=0, atol=0)
+    np.testing.assert_allclose(oracle.star2d_at(a, nx, ny, nz, r, c[:2], idx),
+                               synth.interior(oracle.star2d(a, nx, ny, nz, r, c[:2]), nx, ny,
+                                              nz)[idx[:, 0], idx[:, 1], idx[:, 2]], rtol=0, atol=0)
 
 
 # -------------------------------------------------------------- box oracle
