@@ -14,6 +14,8 @@ Besides the headline the same JSON line carries, each measured in this run:
   * "split_mfma": the radius-4 and radius-3 boxes three ways (FP32 VALU, BF16x3
     and FP16x3S split MFMA, plus the BF16x1 error report);
   * "rtm": the 400^3, 2000-step acoustic forward model with FP64 imaging;
+  * "table1": every kernel of the paper's Table I at 512^3 (the 2-D ones on each
+    plane of the 512^3 stack), with HBM and FP32-FMA roofline fractions;
   * "vti": the 400^3, 1000-step pseudo-acoustic VTI forward model (two fields);
   * "gradient": the 256^3, 1000-step adjoint gradient with checkpointing,
     with its dot-product test;
@@ -51,12 +53,13 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=100)
-    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=512, help="headline grid edge")
     p.add_argument("--only", default="", help="profile one kernel: star|box2|box4|box4_bf16x3|"
-                   "box4_fp16x3s|box3_bf16x3|wave|vti|copy")
+                   "box4_fp16x3s|box3_bf16x3|wave|vti|copy|2DStarR2|2DStarR4|2DBoxR2|2DBoxR3|"
+                   "3DStarR2|3DBoxR1")
     p.add_argument("--skip", default="", help="comma list of extras to skip: "
-                   "split,rtm,vti,gradient,cpu,check")
+                   "split,table1,rtm,vti,gradient,cpu,check")
     p.add_argument("--cpu-planes", type=int, default=0, help="oracle sample depth (0 = full grid)")
     p.add_argument("--collect", action="store_true",
                    help="run rocprofv3 (kernel trace, FETCH_SIZE, WRITE_SIZE) as child processes "
@@ -84,6 +87,29 @@ class Timer:
 
     def reset(self):
         self.pairs = {}
+
+
+def time_launches(torch, f, warm_ms=60.0, min_ms=150.0):
+    """Mean ms per launch of f on torch's current stream.  The GPU is first kept busy
+    for warm_ms (clocks ramp up after idle periods), then launches are timed in one
+    event pair over at least min_ms."""
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    a, b = ev(), ev()
+    a.record()
+    f()
+    b.record()
+    torch.cuda.synchronize()
+    est = max(a.elapsed_time(b), 1e-3)
+    for _ in range(int(warm_ms / est) + 1):
+        f()
+    torch.cuda.synchronize()
+    reps = max(10, int(min_ms / est))
+    a.record()
+    for _ in range(reps):
+        f()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
 
 
 def sample_points(n, count, seed):
@@ -222,6 +248,9 @@ def main():
     if "split" not in skip:
         result["split_mfma"] = bench_split(torch, mms, synth, grid, x, x_np, n, c_box4, c_box3,
                                            dev, "check" not in skip)
+    if "table1" not in skip:
+        result["table1"] = bench_table1(torch, mms, synth, grid, x, x_np, n, dev,
+                                        "check" not in skip)
     del outs
     if "rtm" not in skip:
         result["rtm"] = bench_rtm(torch, mms, synth, dev)
@@ -245,17 +274,7 @@ def bench_split(torch, mms, synth, grid, x, x_np, n, c_box4, c_box3, dev, check)
         ref = oracle.box_at(x64, n, n, n, r, c, sel) if check else None
         for prec in ("fp32", "bf16x3", "fp16x3s", "bf16x1"):
             f = lambda: mms.stencil_apply(x, out, grid, "box", r, c, precision=prec)
-            for _ in range(2):
-                f()
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            reps = 10
-            a.record()
-            for _ in range(reps):
-                f()
-            b.record()
-            torch.cuda.synchronize()
-            ms = a.elapsed_time(b) / reps
+            ms = time_launches(torch, f)
             gpts = grid.points / (ms * 1e-3) / 1e9
             e = {"ms": ms, "gpoints_s": gpts}
             flop = 2 * (2 * r + 1) ** 3
@@ -321,6 +340,48 @@ def bench_rtm(torch, mms, synth, dev, n=400, nt=2000):
         if with_image:
             res["trace_max_abs"] = float(traces.abs().max().item())
             res["image_sum"] = float(image.sum().item())
+    return res
+
+
+def table1_kernels(synth):
+    """Table I kernels: name -> (shape, radius, coefficients, pattern in the table)."""
+    return {
+        "2DStarR2": ("star2d", 2, synth.star2d_coeffs_laplacian(2), "memory"),
+        "2DStarR4": ("star2d", 4, synth.star2d_coeffs_laplacian(4), "memory"),
+        "2DBoxR2": ("box2d", 2, synth.box2d_coeffs(12, 2), "memory"),
+        "2DBoxR3": ("box2d", 3, synth.box2d_coeffs(13, 3), "both"),
+        "3DStarR2": ("star", 2, synth.star_coeffs_laplacian(2), "memory"),
+        "3DStarR4": ("star", 4, synth.star_coeffs_laplacian(4), "memory"),
+        "3DBoxR1": ("box", 1, synth.box_coeffs(11, 1), "memory"),
+        "3DBoxR2": ("box", 2, synth.box_coeffs(3, 2), "compute"),
+    }
+
+
+def bench_table1(torch, mms, synth, grid, x, x_np, n, dev, check):
+    """Every Table I kernel on the 512^3 grid (2-D kernels on each of its planes), FP32."""
+    import oracle
+    out = grid.zeros(dev)
+    res = {}
+    x64 = x_np.astype(np.float64) if check else None
+    sel = sample_points(n, 1000, 16)
+    at = {"star": oracle.star_at, "box": oracle.box_at, "star2d": oracle.star2d_at,
+          "box2d": oracle.box2d_at}
+    for name, (shape, r, c, pattern) in table1_kernels(synth).items():
+        f = lambda: mms.stencil_apply(x, out, grid, shape, r, c)
+        ms = time_launches(torch, f)
+        gpts = grid.points / (ms * 1e-3) / 1e9
+        npts = c.size if shape in ("box", "box2d") else (c.shape[0] * (2 * r + 1) - c.shape[0] + 1)
+        flop = 2 * int(npts)
+        e = {"shape": shape, "radius": r, "points": int(npts), "table_pattern": pattern,
+             "ms": ms, "gpoints_s": gpts, "gbs": gpts * 8.0, "hbm_frac": gpts * 8.0 / HBM_PEAK_GBS,
+             "tflops": gpts * flop / 1e3, "valu_frac": gpts * flop / 1e3 / FP32_VALU_PEAK_TF}
+        if check:
+            o = out.cpu().numpy()
+            got = o[sel[:, 0] + 4, sel[:, 1] + 4, sel[:, 2] + 4]
+            e["rel_max"], e["rel_rms"] = errors(got, at[shape](x64, n, n, n, r, c, sel))
+        res[name] = e
+        log(f"[bench] {name}: {gpts:.1f} Gpoints/s, {e['gbs']:.0f} GB/s ({e['hbm_frac']:.2f} "
+            f"HBM), {e['tflops']:.1f} TFLOP/s")
     return res
 
 
@@ -756,6 +817,9 @@ def profile_only(args, torch, mms, synth, grid, x, outs, sweeps, c_box4, c_box3,
         f = lambda: mms.stencil_apply(x, out, grid, "box", r, c, precision=prec)
     elif k == "copy":
         f = lambda: out.copy_(x)
+    elif k in table1_kernels(synth):
+        shape, r, c, _ = table1_kernels(synth)[k]
+        f = lambda: mms.stencil_apply(x, out, grid, shape, r, c)
     elif k == "vti":
         n = 400
         s, g4, ta, tb, c2, fsrc, shrink = vti_problem(torch, mms, synth, dev, n, 64)

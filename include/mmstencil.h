@@ -39,13 +39,16 @@ extern "C" {
 /* error codes */
 #define MMS_OK 0
 #define MMS_EINVAL (-1)       /* null pointer, bad layout, bad sizes, aliasing   */
-#define MMS_EUNSUPPORTED (-2) /* radius outside 1..4, split precision on a star  */
+#define MMS_EUNSUPPORTED (-2) /* radius outside 1..4, unknown shape, split precision other than on a 3-D box */
 #define MMS_EHIP (-3)         /* HIP runtime or launch error (see mms_last_error)*/
 #define MMS_ENOMEM (-4)       /* a library-owned buffer could not be allocated  */
 
-/* stencil shapes (Sec. I: star = axes only, box = full (2r+1)^3 cube) */
+/* stencil shapes (Sec. I: star = axes only, box = full (2r+1)^d cube; the 2-D
+   shapes are the 2DStar / 2DBox kernels of Table I, applied to every z-plane) */
 #define MMS_STAR 0
 #define MMS_BOX 1
+#define MMS_STAR2D 2
+#define MMS_BOX2D 3
 
 /* arithmetic of a box sweep */
 #define MMS_FP32 0     /* FP32 FMA on the vector ALUs                                 */
@@ -68,11 +71,14 @@ typedef struct mms_grid {
  *   star: out(p) = sum_{axis a} sum_{k=-r..r} coeffs[a][k+r] * in(p + k e_a),
  *         coeffs is [3][2r+1] with axis order z, y, x (ncoeffs = 3(2r+1));
  *   box:  out(p) = sum_{dz,dy,dx} coeffs[dz+r][dy+r][dx+r] * in(p + (dz,dy,dx)),
- *         ncoeffs = (2r+1)^3.
+ *         ncoeffs = (2r+1)^3;
+ *   star2d: out(z,y,x) = sum_k coeffs[0][k+r] in(z,y+k,x) + sum_k coeffs[1][k+r] in(z,y,x+k),
+ *         ncoeffs = 2(2r+1) (axis y, then x); no z neighbour is read;
+ *   box2d: out(z,y,x) = sum_{dy,dx} coeffs[dy+r][dx+r] in(z,y+dy,x+dx), ncoeffs = (2r+1)^2.
  * in, out: device grids with the same layout g; out's halo is not written; in
  * and out must not overlap (MMS_EINVAL).  coeffs: HOST pointer, read during the
- * call only.  radius: 1..4.  precision: MMS_FP32 for the star; any of the four
- * for the box.  The box MFMA variants recast each (dz, dy) pair of the sweep as
+ * call only.  radius: 1..4.  precision: MMS_FP32 for the star and the 2-D
+ * shapes; any of the four for the box.  The box MFMA variants recast each (dz, dy) pair of the sweep as
  * a banded Toeplitz product along x, the matrix-unit mapping of Sec. IV-A, with
  * the (2r+1)^2 one-dimensional stencils of the box decomposition of Sec. IV-C.
  */
@@ -204,7 +210,7 @@ int mms_flat_misfit_f64(const float *a, const float *b, float *resid, int64_t n,
  */
 int mms_dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, void *stream);
 
-/* Tuning of the star and box launches (z-chunk length; 0 = automatic). */
+/* Tuning of the sweep launches: z-chunk length per shape and precision (0 = automatic). */
 int mms_set_zchunk(int shape, int precision, int zchunk);
 
 const char *mms_strerror(int code);

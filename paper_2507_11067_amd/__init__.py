@@ -15,14 +15,14 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (MMS_BF16X1, MMS_BF16X3, MMS_BOX, MMS_FP16X3S, MMS_FP32, MMS_STAR, MmsError,
-                   check, lib)
+from ._lib import (MMS_BF16X1, MMS_BF16X3, MMS_BOX, MMS_BOX2D, MMS_FP16X3S, MMS_FP32, MMS_STAR,
+                   MMS_STAR2D, MmsError, check, lib)
 
 __all__ = ["Grid", "stencil_apply", "Wave", "dot", "flat_dot", "flat_misfit", "dense_to_grid",
            "set_zchunk", "MmsError", "PRECISIONS", "SHAPES"]
 
 PRECISIONS = {"fp32": MMS_FP32, "bf16x3": MMS_BF16X3, "fp16x3s": MMS_FP16X3S, "bf16x1": MMS_BF16X1}
-SHAPES = {"star": MMS_STAR, "box": MMS_BOX}
+SHAPES = {"star": MMS_STAR, "box": MMS_BOX, "star2d": MMS_STAR2D, "box2d": MMS_BOX2D}
 
 
 @dataclass(frozen=True)
@@ -91,7 +91,7 @@ def _dev_ptr(t: torch.Tensor | None, name: str, dtype, numel: int | None = None)
 
 def stencil_apply(inp: torch.Tensor, out: torch.Tensor, grid: Grid, shape: str, radius: int,
                   coeffs, precision: str = "fp32", stream=None) -> torch.Tensor:
-    """One sweep out = S(inp) (star or box, radius 1..4), see mms_stencil_apply."""
+    """One sweep out = S(inp) (star, box, star2d or box2d, radius 1..4), see mms_stencil_apply."""
     c = torch.as_tensor(coeffs, dtype=torch.float32).detach().cpu().contiguous().reshape(-1)
     g = grid.c()
     rc = lib().mms_stencil_apply(_grid_ptr(inp, grid, "inp"), _grid_ptr(out, grid, "out"),

@@ -7,7 +7,7 @@ import os
 from ._build import LIB
 
 MMS_OK, MMS_EINVAL, MMS_EUNSUPPORTED, MMS_EHIP, MMS_ENOMEM = 0, -1, -2, -3, -4
-MMS_STAR, MMS_BOX = 0, 1
+MMS_STAR, MMS_BOX, MMS_STAR2D, MMS_BOX2D = 0, 1, 2, 3
 MMS_FP32, MMS_BF16X3, MMS_FP16X3S, MMS_BF16X1 = 0, 1, 2, 3
 
 EXPORTS = ("mms_stencil_apply", "mms_wave_step", "mms_wave_record", "mms_wave_forward",

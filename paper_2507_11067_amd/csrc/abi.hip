@@ -29,7 +29,7 @@ int reduce_partials_count();
 
 namespace {
 thread_local char g_last[256] = "";
-int g_zchunk[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+int g_zchunk[4][4] = {};
 
 // per-device buffer of FP64 partial sums used by the reductions
 constexpr int kMaxDev = 64;
@@ -84,7 +84,7 @@ bool overlap(const void *a, int64_t abytes, const void *b, int64_t bbytes) {
 }
 
 int zchunk_override(int shape, int precision) {
-    if (shape < 0 || shape > 1 || precision < 0 || precision > 3) return 0;
+    if (shape < 0 || shape > 3 || precision < 0 || precision > 3) return 0;
     return g_zchunk[shape][precision];
 }
 
@@ -112,7 +112,7 @@ const char *mms_strerror(int code) {
 const char *mms_last_error(void) { return g_last; }
 
 int mms_set_zchunk(int shape, int precision, int zchunk) {
-    if (shape < 0 || shape > 1 || precision < 0 || precision > 3 || zchunk < 0) return MMS_EINVAL;
+    if (shape < 0 || shape > 3 || precision < 0 || precision > 3 || zchunk < 0) return MMS_EINVAL;
     g_zchunk[shape][precision] = zchunk;
     return MMS_OK;
 }
@@ -120,19 +120,22 @@ int mms_set_zchunk(int shape, int precision, int zchunk) {
 int mms_stencil_apply(const float *in, float *out, const mms_grid *g, int shape, int radius,
                       const float *coeffs, int ncoeffs, int precision, void *stream) {
     if (radius < 1 || radius > 4) return MMS_EUNSUPPORTED;
-    if (shape != MMS_STAR && shape != MMS_BOX) return MMS_EUNSUPPORTED;
+    if (shape < MMS_STAR || shape > MMS_BOX2D) return MMS_EUNSUPPORTED;
     if (precision < MMS_FP32 || precision > MMS_BF16X1) return MMS_EUNSUPPORTED;
-    if (shape == MMS_STAR && precision != MMS_FP32) return MMS_EUNSUPPORTED;
+    if (shape != MMS_BOX && precision != MMS_FP32) return MMS_EUNSUPPORTED;
     if (!in || !out || !coeffs || !g) return MMS_EINVAL;
     if (!grid_ok(g, radius)) return MMS_EINVAL;
     if (!aligned16(in) || !aligned16(out)) return MMS_EINVAL;
     const int w = 2 * radius + 1;
-    if (ncoeffs != (shape == MMS_STAR ? 3 * w : w * w * w)) return MMS_EINVAL;
+    const int need[4] = {3 * w, w * w * w, 2 * w, w * w};
+    if (ncoeffs != need[shape]) return MMS_EINVAL;
     const int64_t bytes = grid_elems(g) * (int64_t)sizeof(float);
     if (overlap(in, bytes, out, bytes)) return MMS_EINVAL;
     if (grid_empty(g)) return MMS_OK;
     hipStream_t s = (hipStream_t)stream;
     if (shape == MMS_STAR) return launch_star(in, out, g, radius, coeffs, s);
+    if (shape == MMS_STAR2D || shape == MMS_BOX2D)
+        return launch_plane2d(in, out, g, shape, radius, coeffs, s);
     if (precision == MMS_FP32) return launch_box_valu(in, out, g, radius, coeffs, s);
     return launch_box_mfma(in, out, g, radius, coeffs, precision, s);
 }

@@ -65,6 +65,20 @@ inline int pick_zchunk_rounds(int nz, int64_t cols, int64_t slots, int zmin, int
     return best;
 }
 
+// Blocks of `kernel` (launched with `threads` threads, no dynamic LDS) that the
+// current device holds at once: CUs times resident blocks per CU.
+inline int64_t launch_slots(const void *kernel, int threads) {
+    int dev = 0, cus = 256, per = 1;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess ||
+        per < 1)
+        per = 1;
+    return (int64_t)cus * per;
+}
+
 // Sweep launchers (host), one per kernel family.  coeffs is a host array.
 int launch_star(const float *in, float *out, const mms_grid *g, int r, const float *coeffs,
                 hipStream_t s);
@@ -72,6 +86,8 @@ int launch_box_valu(const float *in, float *out, const mms_grid *g, int r, const
                     hipStream_t s);
 int launch_box_mfma(const float *in, float *out, const mms_grid *g, int r, const float *coeffs,
                     int precision, hipStream_t s);
+int launch_plane2d(const float *in, float *out, const mms_grid *g, int shape, int r,
+                   const float *coeffs, hipStream_t s);
 
 }  // namespace mms
 

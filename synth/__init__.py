@@ -24,6 +24,8 @@ HALO = 4
 # difference at unit spacing, as the workload fixes them: centre, then k=1..4.
 LAPLACIAN_R4 = (Fraction(-205, 72), Fraction(8, 5), Fraction(-1, 5),
                 Fraction(8, 315), Fraction(-1, 560))
+# 4th-order (radius-2) weights, used by the radius-2 stars of Table I
+LAPLACIAN_R2 = (Fraction(-5, 2), Fraction(4, 3), Fraction(-1, 12))
 
 
 def row_pitch(nx: int, halo: int = HALO, align: int = 4) -> int:
@@ -53,10 +55,11 @@ def uniform_grid(seed: int, nx: int, ny: int, nz: int, halo: int = HALO,
 
 
 def laplacian_weights(radius: int = 4) -> np.ndarray:
-    """FP32 per-axis weights [k = -r..r] of the workload's radius-4 Laplacian."""
-    if radius != 4:
-        raise ValueError("the workload fixes radius-4 weights only")
-    half = [float(f) for f in LAPLACIAN_R4]
+    """FP32 per-axis weights [k = -r..r] of the radius-4 (8th-order) or radius-2
+    (4th-order) Laplacian."""
+    if radius not in (2, 4):
+        raise ValueError("Laplacian weights are fixed for radius 2 and 4 only")
+    half = [float(f) for f in (LAPLACIAN_R4 if radius == 4 else LAPLACIAN_R2)]
     return np.array(half[:0:-1] + half, dtype=np.float32)
 
 
@@ -64,6 +67,21 @@ def star_coeffs_laplacian(radius: int = 4) -> np.ndarray:
     """Star coefficient table [axis z, y, x][k = -r..r] (FP32) for the Laplacian."""
     w = laplacian_weights(radius)
     return np.stack([w, w, w]).astype(np.float32)
+
+
+def star2d_coeffs_laplacian(radius: int = 4) -> np.ndarray:
+    """2-D star table [axis y, x][k = -r..r] (FP32) for the Laplacian."""
+    w = laplacian_weights(radius)
+    return np.stack([w, w]).astype(np.float32)
+
+
+def box2d_coeffs(seed: int, radius: int) -> np.ndarray:
+    """2-D box weights [dy][dx]: uniform [-1, 1) in FP64, mean removed, cast to FP32."""
+    rng = np.random.default_rng(seed)
+    n = 2 * radius + 1
+    c = rng.uniform(-1.0, 1.0, (n, n))
+    c -= c.mean()
+    return c.astype(np.float32)
 
 
 def star_coeffs_random(seed: int, radius: int) -> np.ndarray:

@@ -48,7 +48,8 @@ FAKE_OUT = ctypes.c_void_p(0x4000000)
 
 
 def apply(L, g, shape=0, r=4, ncoeffs=None, prec=0, inp=FAKE_IN, out=FAKE_OUT, coeffs=True):
-    n = ncoeffs if ncoeffs is not None else (3 * (2 * r + 1) if shape == 0 else (2 * r + 1) ** 3)
+    w = 2 * r + 1
+    n = ncoeffs if ncoeffs is not None else {0: 3 * w, 1: w ** 3, 2: 2 * w, 3: w * w}.get(shape, 1)
     buf = (ctypes.c_float * max(n, 1))()
     c = ctypes.cast(buf, ctypes.POINTER(ctypes.c_float)) if coeffs else None
     return L.mms_stencil_apply(inp, out, ctypes.byref(g) if g is not None else None, shape, r,
@@ -59,8 +60,14 @@ def test_stencil_apply_validation(L):
     EINVAL, EUNS = -1, -2
     assert apply(L, grid(), r=0) == EUNS
     assert apply(L, grid(), r=5) == EUNS
-    assert apply(L, grid(), shape=2) == EUNS
+    assert apply(L, grid(), shape=4) == EUNS
+    assert apply(L, grid(), shape=-1) == EUNS
     assert apply(L, grid(), shape=0, prec=1) == EUNS        # split precision on a star
+    assert apply(L, grid(), shape=2, prec=1) == EUNS        # ... or on a 2-D shape
+    assert apply(L, grid(), shape=3, prec=3) == EUNS
+    assert apply(L, grid(), shape=2, ncoeffs=27) == EINVAL  # star2d takes 2(2r+1)
+    assert apply(L, grid(), shape=3, ncoeffs=80) == EINVAL  # box2d takes (2r+1)^2
+    assert apply(L, grid(H=2), shape=3, r=4) == EINVAL      # x/y halo < radius
     assert apply(L, grid(), prec=7) == EUNS
     assert apply(L, None) == EINVAL
     assert apply(L, grid(), inp=None) == EINVAL

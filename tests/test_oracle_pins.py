@@ -54,6 +54,7 @@ def moment_solve(r):
 
 def test_laplacian_weights_closed_form():
     assert fornberg_second_derivative(4) == list(synth.LAPLACIAN_R4)
+    assert fornberg_second_derivative(2) == list(synth.LAPLACIAN_R2)
     assert moment_solve(4) == list(synth.LAPLACIAN_R4)
     for r in (1, 2, 3):
         assert fornberg_second_derivative(r) == moment_solve(r)
