@@ -50,6 +50,11 @@ class _Wave(ctypes.Structure):
                 ("nt", ctypes.c_int)]
 
 
+class _Tti(ctypes.Structure):
+    _fields_ = [("eps", _dp), ("delta", _dp), ("theta", _dp), ("phi", _dp),
+                ("sigma", ctypes.c_double), ("alpha", ctypes.c_double), ("d1", _dp)]
+
+
 def _load():
     global _lib
     if _lib is None:
@@ -74,6 +79,10 @@ def _load():
         lib.orc_wave_adjoint.argtypes = [wp, _dp, _dp, _dp, _dp, _dp, _dp]
         lib.orc_vti_step.argtypes = [wp, ctypes.c_int] + [_dp] * 9
         lib.orc_vti_forward.argtypes = [wp] + [_dp] * 8
+        tp = ctypes.POINTER(_Tti)
+        lib.orc_tti_operators.argtypes = [wp, tp, _dp, _dp, _dp]
+        lib.orc_tti_step.argtypes = [wp, tp, ctypes.c_int] + [_dp] * 7
+        lib.orc_tti_forward.argtypes = [wp, tp] + [_dp] * 6
         _lib = lib
     return _lib
 
@@ -259,6 +268,40 @@ class Wave:
                              _ptr(arrs[1]), _ptr(hn), _ptr(arrs[2]), _ptr(arrs[3]), _ptr(vn),
                              _ptr(tr))
         return hn, vn, tr
+
+    def tti(self, eps, delta, theta, phi, sigma, alpha, d1):
+        """Bind TTI medium fields (padded) and parameters; returns the handle for tti_*."""
+        keep = [_f64(a) for a in (eps, delta, theta, phi)] + [_f64(d1)]
+        t = _Tti(_ptr(keep[0]), _ptr(keep[1]), _ptr(keep[2]), _ptr(keep[3]), float(sigma),
+                 float(alpha), _ptr(keep[4]))
+        return (t, keep)
+
+    def tti_operators(self, tti, f):
+        """(L f, H1 f) on the interior (Sec. II-A operators, Sec. IV-G mixed derivatives)."""
+        ff = _f64(f)
+        lf, h1 = self.zeros(), self.zeros()
+        _load().orc_tti_operators(ctypes.byref(self._s), ctypes.byref(tti[0]), _ptr(ff), _ptr(lf),
+                                  _ptr(h1))
+        return lf, h1
+
+    def tti_step(self, tti, n, pp, pc, qp, qc):
+        """TTI pair (Sec. II-A): returns (p^{n+1}, q^{n+1}, receiver plane of p^n)."""
+        arrs = [_f64(t) for t in (pp, pc, qp, qc)]
+        pn, qn = self.zeros(), self.zeros()
+        tr = np.zeros((self.ny, self.nx))
+        _load().orc_tti_step(ctypes.byref(self._s), ctypes.byref(tti[0]), n, _ptr(arrs[0]),
+                             _ptr(arrs[1]), _ptr(pn), _ptr(arrs[2]), _ptr(arrs[3]), _ptr(qn),
+                             _ptr(tr))
+        return pn, qn, tr
+
+    def tti_forward(self, tti, p0, p1, q0, q1):
+        """Returns dict(traces of p [nt][ny][nx], last = (p^{nt-1}, p^nt, q^{nt-1}, q^nt))."""
+        arrs = [_f64(t) for t in (p0, p1, q0, q1)]
+        tr = np.zeros((self.nt, self.ny, self.nx))
+        last = np.zeros((4,) + self.shape)
+        _load().orc_tti_forward(ctypes.byref(self._s), ctypes.byref(tti[0]),
+                                *[_ptr(t) for t in arrs], _ptr(tr), _ptr(last))
+        return {"traces": tr, "last": last}
 
     def vti_forward(self, a, b, h0, h1, v0, v1):
         """Returns dict(traces of H [nt][ny][nx], last = (H^{nt-1}, H^nt, V^{nt-1}, V^nt))."""

@@ -23,7 +23,10 @@
  *    + source, with the damping sponge, source and receiver reading listed in
  *    the design notes;
  *  - the adjoint step and the gradient: the exact transpose of that recurrence
- *    (derived in the design notes; the paper has no adjoint).
+ *    (derived in the design notes; the paper has no adjoint);
+ *  - the VTI and TTI pseudo-acoustic pairs of Sec. II-A, with the mixed second
+ *    derivatives of the TTI operators composed from first-derivative stencils
+ *    (Sec. IV-G).
  */
 #include <math.h>
 #include <stddef.h>
@@ -485,4 +488,147 @@ void orc_vti_forward(const orc_wave *w, const double *a, const double *b, const 
     }
     for (int i = 0; i < 3; ++i) { free(H[i]); free(V[i]); }
     free(w1); free(w2); free(w3); free(w4); free(G);
+}
+
+/* ------------------------------------------------------------------ TTI
+ * Pseudo-acoustic TTI pair (Sec. II-A), in units of C2 = (v_pz dt / h)^2:
+ *   p'' = C2 [ (1+2eps) H2 p + alpha H1 q + sigma H1 (p - alpha q) ]
+ *   q'' = C2 [ ((1+2delta)/alpha) H2 p + H1 q - sigma H2 (p/alpha - q) ]
+ * with v_px^2 = (1+2eps) v_pz^2, v_pn^2 = (1+2delta) v_pz^2, sigma = v_sz^2 / v_pz^2,
+ *   H1 = st^2 cp^2 Dxx + st^2 sp^2 Dyy + ct^2 Dzz + st^2 sin(2phi) Dxy
+ *        + sin(2theta) sp Dyz + sin(2theta) cp Dxz      (st = sin theta, cp = cos phi ...)
+ *   H2 = Dxx + Dyy + Dzz - H1.
+ * Second derivatives along an axis are the per-axis star weights; a mixed
+ * derivative Da Db is the product of two first-derivative stencils
+ * D f(i) = sum_{k=1..r} d_k (f(i+k) - f(i-k)), i.e. the 2-D stencil with weights
+ * d_i d_j on the plane of the two axes (Sec. IV-G builds it by composing the two
+ * one-dimensional stencils).  Grid values are read as stored (halo included). */
+typedef struct {
+    const double *eps, *delta, *theta, *phi; /* padded fields */
+    double sigma;                            /* v_sz^2 / v_pz^2 */
+    double alpha;                            /* coupling scale of q */
+    const double *d1;                        /* first-derivative weights d_1..d_r */
+} orc_tti;
+
+static double axis_d2(const double *f, const orc_grid *g, const double *lap, int r, long z, long y,
+                      long x, int az, int ay, int ax) {
+    double s = lap[0] * f[at(g, z, y, x)];
+    for (int k = 1; k <= r; ++k)
+        s += lap[k] * (f[at(g, z + k * az, y + k * ay, x + k * ax)] +
+                       f[at(g, z - k * az, y - k * ay, x - k * ax)]);
+    return s;
+}
+
+/* Da Db f with a = (az, ay, ax), b = (bz, by, bx) unit axis vectors */
+static double mixed_d2(const double *f, const orc_grid *g, const double *d1, int r, long z, long y,
+                       long x, const int *a, const int *b) {
+    double s = 0.0;
+    for (int i = 1; i <= r; ++i)
+        for (int j = 1; j <= r; ++j) {
+            const double pp = f[at(g, z + i * a[0] + j * b[0], y + i * a[1] + j * b[1], x + i * a[2] + j * b[2])];
+            const double pm = f[at(g, z + i * a[0] - j * b[0], y + i * a[1] - j * b[1], x + i * a[2] - j * b[2])];
+            const double mp = f[at(g, z - i * a[0] + j * b[0], y - i * a[1] + j * b[1], x - i * a[2] + j * b[2])];
+            const double mm = f[at(g, z - i * a[0] - j * b[0], y - i * a[1] - j * b[1], x - i * a[2] - j * b[2])];
+            s += d1[i - 1] * d1[j - 1] * (pp - pm - mp + mm);
+        }
+    return s;
+}
+
+/* (L f, H1 f) at one interior point; L = Dxx + Dyy + Dzz */
+static void tti_ops(const orc_wave *w, const orc_tti *t, const double *f, long z, long y, long x,
+                    double *lf, double *h1f) {
+    static const int EX[3] = {0, 0, 1}, EY[3] = {0, 1, 0}, EZ[3] = {1, 0, 0};
+    const orc_grid *g = &w->g;
+    const int r = w->r;
+    const double dxx = axis_d2(f, g, w->lap, r, z, y, x, 0, 0, 1);
+    const double dyy = axis_d2(f, g, w->lap, r, z, y, x, 0, 1, 0);
+    const double dzz = axis_d2(f, g, w->lap, r, z, y, x, 1, 0, 0);
+    const double dxy = mixed_d2(f, g, t->d1, r, z, y, x, EX, EY);
+    const double dyz = mixed_d2(f, g, t->d1, r, z, y, x, EY, EZ);
+    const double dxz = mixed_d2(f, g, t->d1, r, z, y, x, EX, EZ);
+    const long i = at(g, z, y, x);
+    const double th = t->theta[i], ph = t->phi[i];
+    const double st = sin(th), ct = cos(th), sp = sin(ph), cp = cos(ph);
+    *lf = dxx + dyy + dzz;
+    *h1f = st * st * cp * cp * dxx + st * st * sp * sp * dyy + ct * ct * dzz +
+           st * st * sin(2.0 * ph) * dxy + sin(2.0 * th) * sp * dyz + sin(2.0 * th) * cp * dxz;
+}
+
+/* L f and H1 f on the interior of a padded field (zero elsewhere) */
+void orc_tti_operators(const orc_wave *w, const orc_tti *t, const double *f, double *lf,
+                       double *h1f) {
+    const orc_grid *g = &w->g;
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) {
+                const long i = at(g, z, y, x);
+                tti_ops(w, t, f, z, y, x, &lf[i], &h1f[i]);
+            }
+}
+
+static void tti_step_with_G(const orc_wave *w, const orc_tti *t, const double *G, int n,
+                            const double *pp, const double *pc, double *pn, const double *qp,
+                            const double *qc, double *qn, double *trace) {
+    const orc_grid *g = &w->g;
+    const double sg = t->sigma, al = t->alpha;
+#pragma omp parallel for schedule(static)
+    for (long z = 0; z < g->nz; ++z)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) {
+                double lp, h1p, lq, h1q;
+                tti_ops(w, t, pc, z, y, x, &lp, &h1p);
+                tti_ops(w, t, qc, z, y, x, &lq, &h1q);
+                const double h2p = lp - h1p, h2q = lq - h1q;
+                const long i = at(g, z, y, x);
+                const double rp = (1.0 + 2.0 * t->eps[i]) * h2p + al * h1q + sg * (h1p - al * h1q);
+                const double rq = (1.0 + 2.0 * t->delta[i]) / al * h2p + h1q - sg * (h2p / al - h2q);
+                pn[i] = G[i] * (2.0 * pc[i] - G[i] * pp[i] + w->c2[i] * rp);
+                qn[i] = G[i] * (2.0 * qc[i] - G[i] * qp[i] + w->c2[i] * rq);
+            }
+    if (n >= 0 && n < w->nt) {
+        const long s = at(g, w->src_z, w->src_y, w->src_x);
+        pn[s] += w->src[n];
+        qn[s] += w->src[n];
+    }
+    if (trace)
+        for (long y = 0; y < g->ny; ++y)
+            for (long x = 0; x < g->nx; ++x) trace[y * g->nx + x] = pc[at(g, 0, y, x)];
+}
+
+void orc_tti_step(const orc_wave *w, const orc_tti *t, int n, const double *pp, const double *pc,
+                  double *pn, const double *qp, const double *qc, double *qn, double *trace) {
+    double *G = sponge_field(w);
+    tti_step_with_G(w, t, G, n, pp, pc, pn, qp, qc, qn, trace);
+    free(G);
+}
+
+/* Forward TTI run from (p^0, p^1, q^0, q^1); traces [nt][ny][nx] of p; last receives
+ * p^{nt-1}, p^nt, q^{nt-1}, q^nt when non-NULL. */
+void orc_tti_forward(const orc_wave *w, const orc_tti *t, const double *p0, const double *p1,
+                     const double *q0, const double *q1, double *traces, double *last) {
+    const orc_grid *g = &w->g;
+    const size_t L = field_len(g);
+    double *G = sponge_field(w);
+    double *P[3], *Q[3];
+    for (int i = 0; i < 3; ++i) {
+        P[i] = calloc(L, sizeof(double));
+        Q[i] = calloc(L, sizeof(double));
+    }
+    memcpy(P[0], p0, L * sizeof(double)); memcpy(P[1], p1, L * sizeof(double));
+    memcpy(Q[0], q0, L * sizeof(double)); memcpy(Q[1], q1, L * sizeof(double));
+    for (long y = 0; y < g->ny; ++y)
+        for (long x = 0; x < g->nx; ++x) traces[y * g->nx + x] = p0[at(g, 0, y, x)];
+    for (int n = 1; n < w->nt; ++n)
+        tti_step_with_G(w, t, G, n, P[(n - 1) % 3], P[n % 3], P[(n + 1) % 3], Q[(n - 1) % 3],
+                        Q[n % 3], Q[(n + 1) % 3], traces + (size_t)n * g->ny * g->nx);
+    if (last) {
+        const int m = w->nt;
+        memcpy(last, P[(m - 1) % 3], L * sizeof(double));
+        memcpy(last + L, P[m % 3], L * sizeof(double));
+        memcpy(last + 2 * L, Q[(m - 1) % 3], L * sizeof(double));
+        memcpy(last + 3 * L, Q[m % 3], L * sizeof(double));
+    }
+    for (int i = 0; i < 3; ++i) { free(P[i]); free(Q[i]); }
+    free(G);
 }

@@ -26,6 +26,8 @@ LAPLACIAN_R4 = (Fraction(-205, 72), Fraction(8, 5), Fraction(-1, 5),
                 Fraction(8, 315), Fraction(-1, 560))
 # 4th-order (radius-2) weights, used by the radius-2 stars of Table I
 LAPLACIAN_R2 = (Fraction(-5, 2), Fraction(4, 3), Fraction(-1, 12))
+# 8th-order central first derivative: D f(i) = sum_k d_k (f(i+k) - f(i-k)), k = 1..4
+FIRST_DERIV_R4 = (Fraction(4, 5), Fraction(-1, 5), Fraction(4, 105), Fraction(-1, 280))
 
 
 def row_pitch(nx: int, halo: int = HALO, align: int = 4) -> int:
@@ -200,5 +202,21 @@ def thomsen_fields(nx: int, ny: int, nz: int, seed: int, sy: int | None = None):
     for vals in (eps_l, del_l):
         a = padded_zeros(nx, ny, nz, sy=sy)
         interior(a, nx, ny, nz)[...] = (vals[layer][:, None, None] * (1 + noise)).astype(np.float32)
+        out.append(a)
+    return out[0], out[1]
+
+
+def tilt_fields(nx: int, ny: int, nz: int, seed: int, theta_max: float = np.pi / 4,
+                sy: int | None = None):
+    """Padded FP32 tilt (theta, from the vertical) and azimuth (phi) fields of a TTI
+    medium: theta smooth in [0, theta_max], phi smooth over [0, 2 pi); zero halo."""
+    from scipy.ndimage import gaussian_filter
+    rng = np.random.default_rng(seed)
+    out = []
+    for lo, hi in ((0.0, theta_max), (0.0, 2 * np.pi)):
+        f = gaussian_filter(rng.standard_normal((nz, ny, nx)), sigma=6.0, mode="reflect")
+        f = (f - f.min()) / max(f.max() - f.min(), 1e-30)
+        a = padded_zeros(nx, ny, nz, sy=sy)
+        interior(a, nx, ny, nz)[...] = (lo + (hi - lo) * f).astype(np.float32)
         out.append(a)
     return out[0], out[1]

@@ -587,3 +587,170 @@ def test_vti_step_matches_forward():
         hp, hc, vp, vc = hc, hn, vc, vn
     np.testing.assert_array_equal(hc, res["last"][1])
     np.testing.assert_array_equal(vc, res["last"][3])
+
+
+# ------------------------------------------------------------------- TTI oracle
+D1 = [float(v) for v in synth.FIRST_DERIV_R4]
+
+
+def first_derivative_closed_form(r):
+    """Central first-derivative weights d_k, k = 1..r, of order 2r:
+    d_k = (-1)^(k+1) (r!)^2 / (k (r-k)! (r+k)!)."""
+    f = math.factorial
+    return [Fraction((-1) ** (k + 1) * f(r) ** 2, k * f(r - k) * f(r + k)) for k in range(1, r + 1)]
+
+
+def test_first_derivative_weights():
+    d = first_derivative_closed_form(4)
+    assert d == list(synth.FIRST_DERIV_R4)
+    # moment conditions: sum_k d_k 2 k^(2j+1) = [j == 0], j = 0..r-1
+    for j in range(4):
+        assert sum(dk * 2 * Fraction(k + 1) ** (2 * j + 1) for k, dk in enumerate(d)) == (j == 0)
+    assert first_derivative_closed_form(1) == [Fraction(1, 2)]
+
+
+def tti_poly(deg, seed, n):
+    """Random polynomial of total degree <= deg on the padded n^3 cube and its exact
+    Hessian (grid units)."""
+    rng = np.random.default_rng(seed)
+    N = n + 8
+    s = n / 2.0
+    idx = (np.arange(N) - 4 - (n - 1) / 2.0) / s
+    Z, Y, X = np.meshgrid(idx, idx, idx, indexing="ij")
+    u = np.zeros((N, N, N))
+    H = {k: np.zeros((N, N, N)) for k in ("xx", "yy", "zz", "xy", "yz", "xz")}
+    P = lambda b, e: b ** e if e >= 0 else 0.0 * b
+    for i in range(deg + 1):
+        for j in range(deg + 1 - i):
+            for k in range(deg + 1 - i - j):
+                a = rng.uniform(-1, 1)
+                u += a * X ** i * Y ** j * Z ** k
+                H["xx"] += a * i * (i - 1) * P(X, i - 2) * Y ** j * Z ** k / s ** 2
+                H["yy"] += a * j * (j - 1) * X ** i * P(Y, j - 2) * Z ** k / s ** 2
+                H["zz"] += a * k * (k - 1) * X ** i * Y ** j * P(Z, k - 2) / s ** 2
+                H["xy"] += a * i * j * P(X, i - 1) * P(Y, j - 1) * Z ** k / s ** 2
+                H["yz"] += a * j * k * X ** i * P(Y, j - 1) * P(Z, k - 1) / s ** 2
+                H["xz"] += a * i * k * P(X, i - 1) * Y ** j * P(Z, k - 1) / s ** 2
+    return u, H
+
+
+def tti_wave(n, nt=4, c2=None, lap=None, src=(0, 0, 0), f=None, W=0, alpha=0.0, faces=0):
+    c2 = synth.padded_zeros(n, n, n, dtype=np.float64) if c2 is None else c2
+    lap = [float(v) for v in synth.LAPLACIAN_R4] if lap is None else lap
+    f = np.zeros(nt) if f is None else f
+    return oracle.Wave(n, n, n, c2, lap, src, f, nt, W, alpha, faces)
+
+
+def test_tti_operators_exact_on_degree_8_polynomials():
+    """H1 = (n . grad)^2 with n = (sin t cos p, sin t sin p, cos t) at every cell, and
+    L = Laplacian, exactly (to rounding) for polynomials of degree <= 8: the mixed
+    derivatives are products of 8th-order first-derivative stencils."""
+    n = 12
+    u, H = tti_poly(8, seed=70, n=n)
+    rng = np.random.default_rng(71)
+    th = rng.uniform(0, np.pi, u.shape)
+    ph = rng.uniform(0, 2 * np.pi, u.shape)
+    w = tti_wave(n)
+    t = w.tti(np.zeros_like(u), np.zeros_like(u), th, ph, 0.0, 1.0, D1)
+    lf, h1 = w.tti_operators(t, u)
+    nx_, ny_, nz_ = np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)
+    want = (nx_ ** 2 * H["xx"] + ny_ ** 2 * H["yy"] + nz_ ** 2 * H["zz"] + 2 * nx_ * ny_ * H["xy"]
+            + 2 * ny_ * nz_ * H["yz"] + 2 * nx_ * nz_ * H["xz"])
+    I = lambda a: synth.interior(a, n, n, n)
+    scale = np.max(np.abs(I(want)))
+    assert np.max(np.abs(I(h1) - I(want))) <= 1e-9 * scale
+    lap = H["xx"] + H["yy"] + H["zz"]
+    assert np.max(np.abs(I(lf) - I(lap))) <= 1e-9 * np.max(np.abs(I(lap)))
+
+
+def test_tti_mixed_derivative_not_exact_at_degree_9():
+    n = 12
+    N = n + 8
+    s = n / 2.0
+    idx = (np.arange(N) - 4 - (n - 1) / 2.0) / s
+    Z, Y, X = np.meshgrid(idx, idx, idx, indexing="ij")
+    u = X ** 9 * Z          # d/dx of x^9 is where the 8th-order stencil first errs
+    want = 9 * X ** 8 / s ** 2
+    th = np.full(u.shape, np.pi / 4)
+    ph = np.zeros(u.shape)  # n = (1, 0, 1)/sqrt 2: H1 = (Dxx + Dzz)/2 + Dxz
+    w = tti_wave(n)
+    t = w.tti(np.zeros_like(u), np.zeros_like(u), th, ph, 0.0, 1.0, D1)
+    _, h1 = w.tti_operators(t, u)
+    exact = 0.5 * 72 * X ** 7 * Z / s ** 2 + want
+    err = np.max(np.abs(synth.interior(h1 - exact, n, n, n)))
+    assert err > 1e-6 * np.max(np.abs(synth.interior(exact, n, n, n)))
+
+
+def tti_medium(n, seed, const_delta=None):
+    rng = np.random.default_rng(seed)
+    eps = synth.padded_zeros(n, n, n, dtype=np.float64)
+    delta = synth.padded_zeros(n, n, n, dtype=np.float64)
+    synth.interior(eps, n, n, n)[...] = rng.uniform(0.1, 0.3, (n, n, n))
+    synth.interior(delta, n, n, n)[...] = (const_delta if const_delta is not None
+                                            else rng.uniform(0.0, 0.1, (n, n, n)))
+    return eps, delta
+
+
+def test_tti_zero_tilt_reduces_to_vti():
+    """theta = 0, sigma = 0, alpha = sqrt(1 + 2 delta): the TTI pair is the VTI pair."""
+    n, nt, d0 = 12, 60, 0.08
+    rng = np.random.default_rng(72)
+    eps, delta = tti_medium(n, 73, const_delta=d0)
+    c2 = synth.padded_zeros(n, n, n, dtype=np.float64)
+    synth.interior(c2, n, n, n)[...] = rng.uniform(0.05, 0.12, (n, n, n))
+    f = rng.standard_normal(nt)
+    w = tti_wave(n, nt, c2, src=(3, 6, 5), f=f, W=3, alpha=0.1, faces=synth.SPONGE_LATERAL_AND_BOTTOM)
+    zero = np.zeros_like(c2)
+    alpha = math.sqrt(1 + 2 * d0)
+    t = w.tti(eps, delta, zero, rng.uniform(0, 6, c2.shape), 0.0, alpha, D1)
+    fields = [synth.smooth_random_grid(74 + k, n, n, n).astype(np.float64) for k in range(4)]
+    tt = w.tti_forward(t, *fields)
+    vt = w.vti_forward(1 + 2 * eps, np.sqrt(1 + 2 * delta), *fields)
+    scale = np.max(np.abs(vt["last"]))
+    assert np.max(np.abs(tt["last"] - vt["last"])) <= 1e-12 * scale
+    np.testing.assert_allclose(tt["traces"], vt["traces"], rtol=0,
+                               atol=1e-12 * np.max(np.abs(vt["traces"])))
+
+
+def test_tti_axis_along_x_is_transposed_vti():
+    """theta = pi/2, phi = 0 puts the symmetry axis on x: the TTI pair equals the VTI
+    pair on the grid with x and z exchanged (no sponge, symmetric source)."""
+    n, nt, d0 = 12, 40, 0.05
+    rng = np.random.default_rng(75)
+    eps, delta = tti_medium(n, 76, const_delta=d0)
+    c2 = synth.padded_zeros(n, n, n, dtype=np.float64)
+    synth.interior(c2, n, n, n)[...] = rng.uniform(0.05, 0.12, (n, n, n))
+    assert c2.shape == (n + 8,) * 3
+    T = lambda a: np.ascontiguousarray(np.swapaxes(a, 0, 2))
+    f = rng.standard_normal(nt)
+    alpha = math.sqrt(1 + 2 * d0)
+    fields = [synth.smooth_random_grid(77 + k, n, n, n).astype(np.float64) for k in range(4)]
+    w = tti_wave(n, nt, c2, src=(6, 6, 6), f=f)
+    t = w.tti(eps, delta, np.full(c2.shape, np.pi / 2), np.zeros(c2.shape), 0.0, alpha, D1)
+    tt = w.tti_forward(t, *fields)
+    wv = tti_wave(n, nt, T(c2), src=(6, 6, 6), f=f)
+    vt = wv.vti_forward(T(1 + 2 * eps), T(np.sqrt(1 + 2 * delta)), *[T(a) for a in fields])
+    got = np.stack([T(a) for a in tt["last"]])
+    scale = np.max(np.abs(vt["last"]))
+    assert np.max(np.abs(got - vt["last"])) <= 1e-11 * scale
+
+
+def test_tti_step_matches_forward():
+    n, nt = 9, 5
+    rng = np.random.default_rng(78)
+    eps, delta = tti_medium(n, 79)
+    th, ph = synth.tilt_fields(n, n, n, 80)
+    c2 = synth.padded_zeros(n, n, n, dtype=np.float64)
+    synth.interior(c2, n, n, n)[...] = rng.uniform(0.05, 0.1, (n, n, n))
+    w = tti_wave(n, nt, c2, src=(2, 4, 4), f=rng.standard_normal(nt), W=3, alpha=0.1,
+                 faces=synth.SPONGE_LATERAL_AND_BOTTOM)
+    t = w.tti(eps, delta, th, ph, 0.1, 1.0, D1)
+    fields = [synth.smooth_random_grid(81 + k, n, n, n).astype(np.float64) for k in range(4)]
+    res = w.tti_forward(t, *fields)
+    pp, pc, qp, qc = fields
+    for k in range(1, nt):
+        pn, qn, tr = w.tti_step(t, k, pp, pc, qp, qc)
+        np.testing.assert_array_equal(tr, res["traces"][k])
+        pp, pc, qp, qc = pc, pn, qc, qn
+    np.testing.assert_array_equal(pc, res["last"][1])
+    np.testing.assert_array_equal(qc, res["last"][3])
