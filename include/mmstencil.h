@@ -180,6 +180,39 @@ int mms_vti_step(const mms_wave *w, int n, const float *a, const float *b, const
                  float *v_next, void *stream);
 
 /*
+ * Medium of the pseudo-acoustic TTI pair (Sec. II-A) for mms_tti_step.
+ */
+typedef struct mms_tti {
+    const float *eps, *delta;  /* Thomsen parameters, device grids (layout g)             */
+    const float *theta, *phi;  /* tilt of the symmetry axis from z and its azimuth from x,  */
+                               /* radians, device grids (layout g)                          */
+    float sigma;               /* v_sz^2 / v_pz^2 (0 gives the pure pseudo-acoustic pair)   */
+    float alpha;               /* scale of q in the coupling, > 0                           */
+    float d1[4];               /* first-derivative weights d_1..d_radius:                   */
+                               /* D f(i) = sum_k d_k (f(i+k) - f(i-k))                       */
+    float *work;               /* device workspace of 4 grids (layout g, 16-byte aligned),  */
+                               /* overwritten by every call; caller-owned                   */
+} mms_tti;
+
+/*
+ * mms_tti_step -- one step n (1 <= n < nt) of the pseudo-acoustic TTI pair (Sec. II-A),
+ * in units of C2 = (v_pz dt / h)^2 (C2 and the rest of the problem from w):
+ *   p'' = C2 [ (1+2eps) H2 p + alpha H1 q + sigma H1 (p - alpha q) ]
+ *   q'' = C2 [ ((1+2delta)/alpha) H2 p + H1 q - sigma H2 (p/alpha - q) ]
+ *   H1 = (n . grad)^2, n = (sin(theta) cos(phi), sin(theta) sin(phi), cos(theta)) in (x, y, z),
+ *   H2 = Dxx + Dyy + Dzz - H1,
+ * stepped as u^{n+1} = G (2 u^n - G u^{n-1} + u'') + src_dt2f[n] delta_src for u = p, q.
+ * Dxx, Dyy, Dzz use the per-axis weights w->lap; the mixed derivatives are products of the
+ * first-derivative stencil t->d1 along the two axes (the composition of one-dimensional
+ * stencils of Sec. IV-G).  traces[n] = p^n(z = 0); the image is not used.  Grid cells are read
+ * as stored, halo included.  p_next may equal p_prev and q_next may equal q_prev; no other
+ * pair of arguments (work included) may overlap.
+ */
+int mms_tti_step(const mms_wave *w, const mms_tti *t, int n, const float *p_prev,
+                 const float *p_cur, float *p_next, const float *q_prev, const float *q_cur,
+                 float *q_next, void *stream);
+
+/*
  * mms_wave_energy -- FP64 discrete energy of the leapfrog scheme without
  * sponge or source, E^{n+1/2} = sum (u^{n+1}-u^n)^2 / C2 - <u^{n+1}, S u^n>,
  * which the scheme conserves exactly for a symmetric S.  *out_dev (device) is

@@ -18,7 +18,7 @@ from . import _lib
 from ._lib import (MMS_BF16X1, MMS_BF16X3, MMS_BOX, MMS_BOX2D, MMS_FP16X3S, MMS_FP32, MMS_STAR,
                    MMS_STAR2D, MmsError, check, lib)
 
-__all__ = ["Grid", "stencil_apply", "Wave", "dot", "flat_dot", "flat_misfit", "dense_to_grid",
+__all__ = ["Grid", "stencil_apply", "Wave", "Tti", "dot", "flat_dot", "flat_misfit", "dense_to_grid",
            "set_zchunk", "MmsError", "PRECISIONS", "SHAPES"]
 
 PRECISIONS = {"fp32": MMS_FP32, "bf16x3": MMS_BF16X3, "fp16x3s": MMS_FP16X3S, "bf16x1": MMS_BF16X1}
@@ -204,6 +204,15 @@ class Wave:
                                  _grid_ptr(v_prev, g, "v_prev"), _grid_ptr(v_cur, g, "v_cur"),
                                  _grid_ptr(v_next, g, "v_next"), _stream(stream)), "mms_vti_step")
 
+    def tti_step(self, n, tti: "Tti", p_prev, p_cur, p_next, q_prev, q_cur, q_next, stream=None):
+        """One pseudo-acoustic TTI step (see mms_tti_step)."""
+        g = self.grid
+        check(lib().mms_tti_step(ctypes.byref(self._w), ctypes.byref(tti._t), int(n),
+                                 _grid_ptr(p_prev, g, "p_prev"), _grid_ptr(p_cur, g, "p_cur"),
+                                 _grid_ptr(p_next, g, "p_next"), _grid_ptr(q_prev, g, "q_prev"),
+                                 _grid_ptr(q_cur, g, "q_cur"), _grid_ptr(q_next, g, "q_next"),
+                                 _stream(stream)), "mms_tti_step")
+
     def energy(self, u_n, u_np1, stream=None) -> float:
         out = torch.zeros(1, dtype=torch.float64, device=u_n.device)
         check(lib().mms_wave_energy(ctypes.byref(self._w), _grid_ptr(u_n, self.grid, "u_n"),
@@ -211,6 +220,21 @@ class Wave:
                                     _dev_ptr(out, "out", torch.float64), _stream(stream)),
               "mms_wave_energy")
         return float(out.item())
+
+
+class Tti:
+    """TTI medium (mms_tti) bound to device tensors; allocates its 4-grid workspace once."""
+
+    def __init__(self, grid: Grid, eps, delta, theta, phi, sigma: float, alpha: float, d1,
+                 device="cuda"):
+        self.grid = grid
+        self.fields = (eps, delta, theta, phi)
+        self.work = torch.empty((4,) + grid.shape, dtype=torch.float32, device=device)
+        d = (ctypes.c_float * 4)(*([float(v) for v in d1] + [0.0] * (4 - len(d1))))
+        self._t = _lib.MmsTti(_grid_ptr(eps, grid, "eps"), _grid_ptr(delta, grid, "delta"),
+                              _grid_ptr(theta, grid, "theta"), _grid_ptr(phi, grid, "phi"),
+                              float(sigma), float(alpha), d,
+                              ctypes.c_void_p(self.work.data_ptr()))
 
 
 def dot(a: torch.Tensor, b: torch.Tensor | None, grid: Grid, stream=None) -> float:

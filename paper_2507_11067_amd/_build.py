@@ -12,7 +12,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmmstencil.so")
 SOURCES = ["abi.hip", "star.hip", "box_valu.hip", "box_mfma.hip", "plane2d.hip", "wave.hip",
-           "vti.hip", "reduce.hip"]
+           "vti.hip", "tti.hip", "reduce.hip"]
 
 # Packed FP32 instructions stay off: only scalar FP32 FMAs are emitted.
 HIPFLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-I" + INCLUDE,

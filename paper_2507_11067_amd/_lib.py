@@ -13,7 +13,7 @@ MMS_FP32, MMS_BF16X3, MMS_FP16X3S, MMS_BF16X1 = 0, 1, 2, 3
 EXPORTS = ("mms_stencil_apply", "mms_wave_step", "mms_wave_record", "mms_wave_forward",
            "mms_wave_adjoint_step", "mms_wave_adjoint", "mms_wave_energy", "mms_dot_f64",
            "mms_flat_dot_f64", "mms_flat_misfit_f64", "mms_dense_to_grid", "mms_set_zchunk",
-           "mms_strerror", "mms_last_error", "mms_abi_version", "mms_vti_step")
+           "mms_strerror", "mms_last_error", "mms_abi_version", "mms_vti_step", "mms_tti_step")
 
 
 class MmsGrid(ctypes.Structure):
@@ -30,6 +30,12 @@ class MmsWave(ctypes.Structure):
                 ("src_z", ctypes.c_int64), ("src_y", ctypes.c_int64), ("src_x", ctypes.c_int64),
                 ("src_dt2f", ctypes.c_void_p), ("traces", ctypes.c_void_p),
                 ("image", ctypes.c_void_p)]
+
+
+class MmsTti(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_void_p), ("delta", ctypes.c_void_p), ("theta", ctypes.c_void_p),
+                ("phi", ctypes.c_void_p), ("sigma", ctypes.c_float), ("alpha", ctypes.c_float),
+                ("d1", ctypes.c_float * 4), ("work", ctypes.c_void_p)]
 
 
 class MmsError(RuntimeError):
@@ -61,6 +67,7 @@ def lib():
                                        vp, vp]
         L.mms_wave_energy.argtypes = [wp, vp, vp, vp, vp]
         L.mms_vti_step.argtypes = [wp, i32] + [vp] * 8 + [vp]
+        L.mms_tti_step.argtypes = [wp, ctypes.POINTER(MmsTti), i32] + [vp] * 6 + [vp]
         L.mms_dot_f64.argtypes = [vp, vp, gp, vp, vp]
         L.mms_flat_dot_f64.argtypes = [vp, vp, i64, vp, vp]
         L.mms_flat_misfit_f64.argtypes = [vp, vp, vp, i64, vp, vp]

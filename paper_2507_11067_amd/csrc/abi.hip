@@ -18,6 +18,8 @@ int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *o
                 int64_t npartials, hipStream_t s);
 int64_t wave_energy_blocks(const mms_wave *w);
 int dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, hipStream_t s);
+int tti_step(const mms_wave *w, const mms_tti *t, int n, const float *pp, const float *pc,
+             float *pn, const float *qp, const float *qc, float *qn, hipStream_t s);
 int vti_step(const mms_wave *w, int n, const float *fa, const float *fb, const float *hp,
              const float *hc, float *hn, const float *vp, const float *vc, float *vn,
              hipStream_t s);
@@ -185,6 +187,39 @@ int mms_vti_step(const mms_wave *w, int n, const float *a, const float *b, const
     if (grid_empty(&w->g)) return MMS_OK;
     return vti_step(w, n, a, b, h_prev, h_cur, h_next, v_prev, v_cur, v_next,
                     (hipStream_t)stream);
+}
+
+int mms_tti_step(const mms_wave *w, const mms_tti *t, int n, const float *p_prev,
+                 const float *p_cur, float *p_next, const float *q_prev, const float *q_cur,
+                 float *q_next, void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!t) return MMS_EINVAL;
+    const float *ins[] = {t->eps, t->delta, t->theta, t->phi, p_prev, p_cur, q_prev, q_cur};
+    for (const float *p : ins)
+        if (!p || !aligned16(p)) return MMS_EINVAL;
+    if (!p_next || !q_next || !t->work || !aligned16(p_next) || !aligned16(q_next) ||
+        !aligned16(t->work))
+        return MMS_EINVAL;
+    if (n < 1 || n >= w->nt) return MMS_EINVAL;
+    if (!(t->alpha > 0.f) || !(t->sigma >= 0.f)) return MMS_EINVAL;
+    const int64_t bytes = grid_elems(&w->g) * (int64_t)sizeof(float);
+    // every read-only operand against both outputs and the workspace
+    const float *ro[] = {t->eps, t->delta, t->theta, t->phi, p_cur, q_cur, w->c2};
+    for (const float *p : ro)
+        if (overlap(p, bytes, p_next, bytes) || overlap(p, bytes, q_next, bytes) ||
+            overlap(p, bytes, t->work, 4 * bytes))
+            return MMS_EINVAL;
+    if (overlap(p_next, bytes, q_next, bytes)) return MMS_EINVAL;
+    if (overlap(p_next, bytes, t->work, 4 * bytes) || overlap(q_next, bytes, t->work, 4 * bytes))
+        return MMS_EINVAL;
+    if (overlap(p_prev, bytes, t->work, 4 * bytes) || overlap(q_prev, bytes, t->work, 4 * bytes))
+        return MMS_EINVAL;
+    if (p_prev != p_next && overlap(p_prev, bytes, p_next, bytes)) return MMS_EINVAL;
+    if (q_prev != q_next && overlap(q_prev, bytes, q_next, bytes)) return MMS_EINVAL;
+    if (overlap(p_prev, bytes, q_next, bytes) || overlap(q_prev, bytes, p_next, bytes))
+        return MMS_EINVAL;
+    if (grid_empty(&w->g)) return MMS_OK;
+    return tti_step(w, t, n, p_prev, p_cur, p_next, q_prev, q_cur, q_next, (hipStream_t)stream);
 }
 
 int mms_wave_record(const mms_wave *w, int n, const float *u, void *stream) {

@@ -100,6 +100,15 @@ __device__ __forceinline__ float4 guarded_load(const float *p, bool ok, const fl
     return ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
+// 16-byte load from p when `ok`, else from `safe`, with no masking of the value.
+// For tile words that lie outside the array: they only feed outputs that are never
+// stored, so their value does not matter, and an unmasked value keeps the compiler
+// from turning the load into a branch (which would force a full wait on every
+// load in flight, the prefetch of the next plane included).
+__device__ __forceinline__ float4 select_load(const float *p, bool ok, const float *safe) {
+    return *reinterpret_cast<const float4 *>(ok ? p : safe);
+}
+
 // Absorbing sponge: g(d) = exp(-(a (W - d))^2) for a cell at distance d < W from a
 // damped face, 1 elsewhere; gaxis is the factor of one axis at interior index i of n.
 __device__ __forceinline__ float mms_g1(int d, int W, float a) {

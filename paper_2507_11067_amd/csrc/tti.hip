@@ -1,0 +1,512 @@
+// Pseudo-acoustic TTI step (gfx950): the two-field update of RTM in tilted
+// transversely isotropic media (Sec. II-A, Sec. V-F), in units of
+// C2 = (v_pz dt / h)^2:
+//   p'' = C2 [ (1+2eps) H2 p + alpha H1 q + sigma H1 (p - alpha q) ]
+//   q'' = C2 [ ((1+2delta)/alpha) H2 p + H1 q - sigma H2 (p/alpha - q) ]
+//   H1 = (n . grad)^2 with n = (sin t cos f, sin t sin f, cos t),  H2 = Laplacian - H1,
+// stepped as u^{n+1} = G (2u^n - G u^{n-1} + dt^2 u'') + dt^2 f^n delta_src.
+//
+// The six second derivatives follow the paper's decomposition into
+// one-dimensional stencils (Sec. IV-G): Dxx, Dyy, Dzz with the per-axis
+// second-derivative weights; the mixed ones as products of first-derivative
+// stencils D (weights d_1..d_r, antisymmetric).  Two passes:
+//  * pass 1 (z only): Dz f and Dzz f of both fields for every cell of the padded
+//    (x, y) extent, streamed through a register queue of 2r+1 planes; written to
+//    a workspace of four grids.  Each plane of the padded array is contiguous,
+//    so a lane owns one 16-byte word of it and the loads are fully coalesced.
+//  * pass 2 (x and y): per plane, the tiles of p, q, Dz p and Dz q with r rows
+//    and 4 cells of halo are staged in a double-buffered LDS tile (the next
+//    plane's tiles are fetched after the current plane's arithmetic, so that no
+//    registers stay reserved for them); Dxx, Dyy and Dxy = Dx(Dy f) come from the p / q tiles, Dxz =
+//    Dx(Dz f) and Dyz = Dy(Dz f) from the Dz tiles; the direction cosines come
+//    from theta / phi per cell; the update is fused with the sponge, source and
+//    receivers; outputs are written with streaming stores.
+#include "mms_internal.h"
+
+namespace mms {
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 f4(float a) { return make_float4(a, a, a, a); }
+
+// sin and cos of an angle of moderate size (the tilt and azimuth fields, |x| up to
+// a few 2 pi): Cody-Waite reduction by pi/2 with a two-term split of pi/2, then the
+// Taylor polynomials of sin (to x^11) and cos (to x^12) on |r| <= pi/4, whose
+// truncation errors (< 1e-12) are far below FP32 rounding.  This keeps the
+// library's general sincosf, with its large-argument path, out of the kernel.
+__device__ __forceinline__ void small_sincos(float x, float *sn, float *cs) {
+    const float q = rintf(x * 0.636619772367581343f);   // x / (pi/2)
+    float r = fmaf(-q, 1.57079637050628662109375f, x);   // pi/2 rounded to FP32
+    r = fmaf(-q, -4.37113900630947659e-8f, r);           // pi/2 minus that
+    const float r2 = r * r;
+    // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
+    float ps = -2.50521083854417188e-8f;                 // -1/11!
+    ps = fmaf(ps, r2, 2.75573192239858907e-6f);          //  1/9!
+    ps = fmaf(ps, r2, -1.98412698412698413e-4f);         // -1/7!
+    ps = fmaf(ps, r2, 8.33333333333333333e-3f);          //  1/5!
+    ps = fmaf(ps, r2, -1.66666666666666667e-1f);         // -1/3!
+    const float s = fmaf(ps * r2, r, r);
+    float pc = 2.08767569878680990e-9f;                  //  1/12!
+    pc = fmaf(pc, r2, -2.75573192239858907e-7f);         // -1/10!
+    pc = fmaf(pc, r2, 2.48015873015873016e-5f);          //  1/8!
+    pc = fmaf(pc, r2, -1.38888888888888889e-3f);         // -1/6!
+    pc = fmaf(pc, r2, 4.16666666666666667e-2f);          //  1/4!
+    pc = fmaf(pc, r2, -0.5f);                            // -1/2!
+    const float c = fmaf(pc, r2, 1.0f);
+    const int k = ((int)q) & 3;
+    *sn = k == 0 ? s : k == 1 ? c : k == 2 ? -s : -c;
+    *cs = k == 0 ? c : k == 1 ? -s : k == 2 ? -c : s;
+}
+
+// ------------------------------------------------------------------ pass 1
+struct DzArgs {
+    const float *p, *q;          // plane 0 of the padded array, z = 0 (interior)
+    float *dzp, *dzq, *dzzp, *dzzq;
+    int64_t plane_words;         // 16-byte words per plane ((ny + 2H) * sy / 4)
+    int64_t sz;                  // plane stride in floats
+    int nz, zchunk, ncol_blocks;
+    float c2w[5];                // second-derivative weights: centre, k = 1..r
+    float d1[4];                 // first-derivative weights d_1..d_r
+};
+
+template <int R>
+__global__ void __launch_bounds__(256) tti_dz_kernel(DzArgs a) {
+    constexpr int Q = 2 * R + 1;
+    const int cb = blockIdx.x % a.ncol_blocks;
+    const int zc = blockIdx.x / a.ncol_blocks;
+    const int64_t word = (int64_t)cb * 256 + threadIdx.x;
+    if (word >= a.plane_words) return;
+    const int zb = zc * a.zchunk;
+    const int ze = min(zb + a.zchunk, a.nz);
+    const int64_t off = word * 4;
+    auto ld = [&](const float *base, int z) -> float4 {
+        return *reinterpret_cast<const float4 *>(base + (int64_t)z * a.sz + off);
+    };
+    float4 qp[Q], qq[Q];
+#pragma unroll
+    for (int i = 0; i < Q - 1; ++i) {
+        qp[i] = ld(a.p, zb - R + i);
+        qq[i] = ld(a.q, zb - R + i);
+    }
+    for (int z = zb; z < ze;) {
+#pragma unroll
+        for (int ph = 0; ph < Q; ++ph) {
+            if (z < ze) {
+                // slot of plane z+k is (ph + R + k) % Q; plane z+R enters now
+                qp[(ph + 2 * R) % Q] = ld(a.p, z + R);
+                qq[(ph + 2 * R) % Q] = ld(a.q, z + R);
+                float4 f[2][2];  // [field][dz, dzz]
+#pragma unroll
+                for (int fi = 0; fi < 2; ++fi) {
+                    const float4 *qu = fi == 0 ? qp : qq;
+                    const float4 c = qu[(ph + R) % Q];
+                    float4 d = f4(0.f), s = make_float4(a.c2w[0] * c.x, a.c2w[0] * c.y,
+                                                        a.c2w[0] * c.z, a.c2w[0] * c.w);
+#pragma unroll
+                    for (int k = 1; k <= R; ++k) {
+                        const float4 up = qu[(ph + R + k) % Q], dn = qu[(ph + R - k + Q) % Q];
+                        const float dk = a.d1[k - 1], ck = a.c2w[k];
+                        d.x = fmaf(dk, up.x - dn.x, d.x);
+                        d.y = fmaf(dk, up.y - dn.y, d.y);
+                        d.z = fmaf(dk, up.z - dn.z, d.z);
+                        d.w = fmaf(dk, up.w - dn.w, d.w);
+                        s.x = fmaf(ck, up.x + dn.x, s.x);
+                        s.y = fmaf(ck, up.y + dn.y, s.y);
+                        s.z = fmaf(ck, up.z + dn.z, s.z);
+                        s.w = fmaf(ck, up.w + dn.w, s.w);
+                    }
+                    f[fi][0] = d;
+                    f[fi][1] = s;
+                }
+                const int64_t o = (int64_t)z * a.sz + off;
+                float *outs[4] = {a.dzp, a.dzzp, a.dzq, a.dzzq};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float4 v = f[i / 2][i % 2];
+                    const f4v vv = {v.x, v.y, v.z, v.w};
+                    __builtin_nontemporal_store(vv, reinterpret_cast<f4v *>(outs[i] + o));
+                }
+                ++z;
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ pass 2
+struct TtiArgs {
+    Geom g;
+    float c2w[5], d1[4];
+    const float *pc, *qc, *dzp, *dzq;   // tiles
+    const float *dzzp, *dzzq, *pp, *qp, *c2, *eps, *delta, *theta, *phi;  // own words
+    float c2s, sigma, alpha;
+    float *pn, *qn;
+    float *traces;
+    const float *src;
+    int src_z, src_y, src_x;
+    int sponge_w;
+    float sponge_a;
+    int faces;
+};
+
+constexpr int NTILE = 4;   // p, q, Dz p, Dz q
+constexpr int NOWN = 9;    // Dzz p, Dzz q, p^{n-1}, q^{n-1}, C2, eps, delta, theta, phi
+
+template <int R, int TX, int TY>
+__global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
+    constexpr int BX = 4 * TX, BY = TY;
+    constexpr int LW4 = TX + 2, LH = BY + 2 * R;
+    constexpr int NT = TX * TY;
+    constexpr int NH = 2 * R * LW4 + 2 * BY;
+    constexpr int NHK = (NH + NT - 1) / NT;
+    __shared__ float4 tile[2][NTILE][LH][LW4];
+
+    const Geom &g = a.g;
+    int b = mms_xcd_remap(blockIdx.x, gridDim.x);
+    const int txi = b % g.ntx;
+    b /= g.ntx;
+    const int tyi = b % g.nty;
+    const int zci = b / g.nty;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int xt = txi * BX, yt = tyi * BY;
+    const int x0 = xt + 4 * tx, y = yt + ty;
+    const int zb = zci * g.zchunk;
+    const int ze = min(zb + g.zchunk, g.nz);
+    const int nx4 = (g.nx + 3) & ~3;
+    const int ylim = g.ny + g.H;
+    const int64_t sy = g.sy, sz = g.sz;
+    const int W = a.sponge_w;
+    const float sa = a.sponge_a;
+
+    const bool own_ok = (x0 <= nx4) && (y < ylim);
+    const int64_t own_off = (int64_t)y * sy + x0;
+    float gown[4];
+    {
+        const float gy = gaxis(y, g.ny, W, sa, a.faces & 4, a.faces & 8);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) gown[e] = gy * gaxis(x0 + e, g.nx, W, sa, a.faces & 1, a.faces & 2);
+    }
+    int64_t h_off[NHK];
+    int h_lds[NHK];
+    bool h_ok[NHK];
+#pragma unroll
+    for (int k = 0; k < NHK; ++k) {
+        const int i = tid + k * NT;
+        int row, lrow, col4, x;
+        if (i < 2 * R * LW4) {
+            const int hr = i / LW4, hc = i % LW4;
+            row = hr < R ? yt - R + hr : yt + BY + (hr - R);
+            lrow = hr < R ? hr : hr + BY;
+            col4 = hc;
+            x = xt - 4 + 4 * hc;
+        } else {
+            const int j = i - 2 * R * LW4;
+            row = yt + j / 2;
+            lrow = R + j / 2;
+            col4 = (j & 1) ? LW4 - 1 : 0;
+            x = (j & 1) ? xt + BX : xt - 4;
+        }
+        h_ok[k] = (i < NH) && (row < ylim) && (x <= nx4);
+        h_off[k] = (int64_t)row * sy + x;
+        h_lds[k] = lrow * LW4 + col4;
+    }
+    const float *tsrc[NTILE] = {a.pc, a.qc, a.dzp, a.dzq};
+    // point-wise operands (theta and phi, the last two, are loaded separately)
+    const float *osrc[NOWN] = {a.dzzp, a.dzzq, a.pp, a.qp, a.c2, a.eps, a.delta, a.theta, a.phi};
+    auto load_tiles = [&](int z, float4 (*tw)[1 + NHK]) {
+        const int64_t zo = (int64_t)z * sz;
+#pragma unroll
+        for (int f = 0; f < NTILE; ++f) {
+            tw[f][0] = select_load(tsrc[f] + zo + own_off, own_ok, a.c2);
+#pragma unroll
+            for (int k = 0; k < NHK; ++k)
+                tw[f][1 + k] = select_load(tsrc[f] + zo + h_off[k], h_ok[k], a.c2);
+        }
+    };
+    auto tile_store = [&](int buf, float4 (*tw)[1 + NHK]) {
+#pragma unroll
+        for (int f = 0; f < NTILE; ++f) {
+            float4 *t = &tile[buf][f][0][0];
+            t[(R + ty) * LW4 + tx + 1] = tw[f][0];
+#pragma unroll
+            for (int k = 0; k < NHK; ++k)
+                if (tid + k * NT < NH) t[h_lds[k]] = tw[f][1 + k];
+        }
+    };
+
+    float4 tw[NTILE][1 + NHK];
+    load_tiles(zb, tw);
+    tile_store(0, tw);
+    __syncthreads();
+
+    const float srcv = a.src ? *a.src : 0.f;
+    const bool zlo = a.faces & 16, zhi = a.faces & 32;
+    for (int z = zb; z < ze; ++z) {
+        const int buf = (z - zb) & 1;
+        const bool more = z + 1 < ze;
+        const int64_t zo = (int64_t)z * sz;
+        // direction cosines of this plane's cells
+        const float4 th4 = select_load(a.theta + zo + own_off, own_ok, a.c2);
+        const float4 ph4 = select_load(a.phi + zo + own_off, own_ok, a.c2);
+        auto comp = [](const float4 &v, int e) {
+            return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+        };
+        // H1 weights per cell: n_x^2, n_y^2, n_z^2, 2 n_x n_y, 2 n_y n_z, 2 n_x n_z
+        float cf[6][4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float st, ct, sp, cp;
+            small_sincos(comp(th4, e), &st, &ct);
+            small_sincos(comp(ph4, e), &sp, &cp);
+            const float nx_ = st * cp, ny_ = st * sp, nz_ = ct;
+            cf[0][e] = nx_ * nx_;
+            cf[1][e] = ny_ * ny_;
+            cf[2][e] = nz_ * nz_;
+            cf[3][e] = 2.f * nx_ * ny_;
+            cf[4][e] = 2.f * ny_ * nz_;
+            cf[5][e] = 2.f * nx_ * nz_;
+        }
+
+        // x/y parts of L f and H1 f for both fields: [field][e]
+        float lxy[2][4], h1[2][4];
+#pragma unroll
+        for (int fi = 0; fi < 2; ++fi) {
+            // one field at a time: stops the scheduler from hoisting every LDS read
+            __builtin_amdgcn_sched_barrier(0);
+            const float4 *t = &tile[buf][fi][0][0] + ty * LW4 + tx;  // window row 0 = y - R
+            float syy[4], sxy[4] = {0.f, 0.f, 0.f, 0.f}, sxx[4];
+            // rows one at a time: unrolling lets the scheduler hoist every row's LDS
+            // words at once, far beyond the register file
+#pragma unroll 1
+            for (int i = 0; i <= 2 * R; ++i) {
+                const int k = i - R;
+                const float4 L = t[i * LW4], C = t[i * LW4 + 1], Rr = t[i * LW4 + 2];
+                const float w[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w, Rr.x, Rr.y, Rr.z, Rr.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    if (k == 0) {
+                        float s2 = a.c2w[0] * w[4 + e];
+#pragma unroll
+                        for (int j = 1; j <= R; ++j) s2 = fmaf(a.c2w[j], w[4 + e + j] + w[4 + e - j], s2);
+                        sxx[e] = s2;
+                        syy[e] = a.c2w[0] * w[4 + e];
+                    } else {
+                        float dx = 0.f;
+#pragma unroll
+                        for (int j = 1; j <= R; ++j) dx = fmaf(a.d1[j - 1], w[4 + e + j] - w[4 + e - j], dx);
+                        const float dk = k > 0 ? a.d1[k - 1] : -a.d1[-k - 1];
+                        sxy[e] = fmaf(dk, dx, sxy[e]);
+                    }
+                }
+            }
+            // y second derivative from the centre words of the window rows
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                const float4 u = t[(R + k) * LW4 + 1], d = t[(R - k) * LW4 + 1];
+                syy[0] = fmaf(a.c2w[k], u.x + d.x, syy[0]);
+                syy[1] = fmaf(a.c2w[k], u.y + d.y, syy[1]);
+                syy[2] = fmaf(a.c2w[k], u.z + d.z, syy[2]);
+                syy[3] = fmaf(a.c2w[k], u.w + d.w, syy[3]);
+            }
+            // Dz tile: x window of the centre row (Dxz), y column of the centre word (Dyz)
+            __builtin_amdgcn_sched_barrier(0);
+            const float4 *tz = &tile[buf][2 + fi][0][0] + ty * LW4 + tx;
+            float sxz[4], syz[4] = {0.f, 0.f, 0.f, 0.f};
+            {
+                const float4 L = tz[R * LW4], C = tz[R * LW4 + 1], Rr = tz[R * LW4 + 2];
+                const float w[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w, Rr.x, Rr.y, Rr.z, Rr.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float s1 = 0.f;
+#pragma unroll
+                    for (int j = 1; j <= R; ++j) s1 = fmaf(a.d1[j - 1], w[4 + e + j] - w[4 + e - j], s1);
+                    sxz[e] = s1;
+                }
+            }
+#pragma unroll
+            for (int j = 1; j <= R; ++j) {
+                const float4 u = tz[(R + j) * LW4 + 1], d = tz[(R - j) * LW4 + 1];
+                const float dj = a.d1[j - 1];
+                syz[0] = fmaf(dj, u.x - d.x, syz[0]);
+                syz[1] = fmaf(dj, u.y - d.y, syz[1]);
+                syz[2] = fmaf(dj, u.z - d.z, syz[2]);
+                syz[3] = fmaf(dj, u.w - d.w, syz[3]);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                lxy[fi][e] = sxx[e] + syy[e];
+                h1[fi][e] = cf[0][e] * sxx[e] + cf[1][e] * syy[e] + cf[3][e] * sxy[e] +
+                            cf[4][e] * syz[e] + cf[5][e] * sxz[e];
+            }
+        }
+        // keep the point-wise loads below the derivative phase (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
+        float4 ow[NOWN];
+#pragma unroll
+        for (int f = 0; f < NOWN - 2; ++f) ow[f] = select_load(osrc[f] + zo + own_off, own_ok, a.c2);
+
+        const float4 *ctrp = &tile[buf][0][0][0] + (R + ty) * LW4 + tx + 1;
+        const float4 *ctrq = &tile[buf][1][0][0] + (R + ty) * LW4 + tx + 1;
+        const float4 pc4 = *ctrp, qc4 = *ctrq;
+        const float pcv[4] = {pc4.x, pc4.y, pc4.z, pc4.w}, qcv[4] = {qc4.x, qc4.y, qc4.z, qc4.w};
+        const float gz = gaxis(z, g.nz, W, sa, zlo, zhi);
+        float rp[4], rq[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float H1[2], H2[2];
+#pragma unroll
+            for (int fi = 0; fi < 2; ++fi) {
+                const float dzz = comp(ow[fi], e);
+                H1[fi] = fmaf(cf[2][e], dzz, h1[fi][e]);
+                H2[fi] = (lxy[fi][e] + dzz) - H1[fi];
+            }
+            const float eps = comp(ow[5], e), del = comp(ow[6], e);
+            const float sg = a.sigma, al = a.alpha;
+            const float accp = (1.f + 2.f * eps) * H2[0] + al * H1[1] + sg * (H1[0] - al * H1[1]);
+            const float accq = (1.f + 2.f * del) / al * H2[0] + H1[1] - sg * (H2[0] / al - H2[1]);
+            const float G = gz * gown[e];
+            const float C2 = a.c2s * comp(ow[4], e);
+            rp[e] = G * (2.0f * pcv[e] - G * comp(ow[2], e) + C2 * accp);
+            rq[e] = G * (2.0f * qcv[e] - G * comp(ow[3], e) + C2 * accq);
+        }
+        if (srcv != 0.f && z == a.src_z && y == a.src_y && a.src_x >= x0 && a.src_x < x0 + 4) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (x0 + e == a.src_x) {
+                    rp[e] += srcv;
+                    rq[e] += srcv;
+                }
+        }
+        if (y < g.ny && x0 < g.nx) {
+            float *pp_ = a.pn + (int64_t)z * sz + own_off;
+            float *qq_ = a.qn + (int64_t)z * sz + own_off;
+            if (x0 + 3 < g.nx) {
+                const f4v vp = {rp[0], rp[1], rp[2], rp[3]};
+                const f4v vq = {rq[0], rq[1], rq[2], rq[3]};
+                __builtin_nontemporal_store(vp, reinterpret_cast<f4v *>(pp_));
+                __builtin_nontemporal_store(vq, reinterpret_cast<f4v *>(qq_));
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (x0 + e < g.nx) {
+                        pp_[e] = rp[e];
+                        qq_[e] = rq[e];
+                    }
+            }
+            if (a.traces && z == 0) {
+                float *pt = a.traces + (int64_t)y * g.nx + x0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (x0 + e < g.nx) pt[e] = pcv[e];
+            }
+        }
+        if (more) {
+            // next plane's tiles into the other buffer; the loads are issued after the
+            // compute so that no register stays reserved for them across it (other
+            // waves cover their latency)
+            load_tiles(z + 1, tw);
+            tile_store(buf ^ 1, tw);
+        }
+        __syncthreads();
+    }
+}
+
+// 256 x 8 tiles, 512 threads: four double-buffered plane tiles fill 135 KB of LDS
+// at radius 4, one block per CU
+constexpr int TTX = 64, TTY = 8;
+
+template <int R>
+int launch_tti(const mms_wave *w, const mms_tti *t, int n, const float *pp, const float *pc,
+               float *pn, const float *qp, const float *qc, float *qn, hipStream_t s) {
+    const mms_grid *gd = &w->g;
+    const int64_t o = (int64_t)gd->halo * (gd->sz + gd->sy + 1);
+    const int64_t L = grid_elems(gd);
+    float *dzp = t->work, *dzq = t->work + L, *dzzp = t->work + 2 * L, *dzzq = t->work + 3 * L;
+    // pass 1 over every word of the interior planes (rows of the y halo included)
+    {
+        DzArgs a{};
+        const int64_t zo = (int64_t)gd->halo * gd->sz;
+        a.p = pc + zo;
+        a.q = qc + zo;
+        a.dzp = dzp + zo;
+        a.dzq = dzq + zo;
+        a.dzzp = dzzp + zo;
+        a.dzzq = dzzq + zo;
+        a.plane_words = (gd->ny + 2 * gd->halo) * gd->sy / 4;
+        a.sz = gd->sz;
+        a.nz = (int)gd->nz;
+        for (int k = 0; k <= R; ++k) a.c2w[k] = w->lap[k];
+        for (int k = 0; k < R; ++k) a.d1[k] = t->d1[k];
+        const int64_t ncb = (a.plane_words + 255) / 256;
+        const int zc = pick_zchunk_rounds(a.nz, ncb, launch_slots(
+            reinterpret_cast<const void *>(&tti_dz_kernel<R>), 256), 8, 128, 2 * R);
+        a.zchunk = zc;
+        a.ncol_blocks = (int)ncb;
+        const int64_t nblk = ncb * ((a.nz + zc - 1) / zc);
+        if (nblk > 0x7fffffff) return MMS_EINVAL;
+        hipLaunchKernelGGL((tti_dz_kernel<R>), dim3((unsigned)nblk), dim3(256), 0, s, a);
+        if (int rc = check_launch("tti_dz_kernel")) return rc;
+    }
+    TtiArgs a{};
+    Geom &g = a.g;
+    g.H = gd->halo;
+    g.nx = (int)gd->nx;
+    g.ny = (int)gd->ny;
+    g.nz = (int)gd->nz;
+    g.sy = gd->sy;
+    g.sz = gd->sz;
+    g.ntx = (g.nx + 4 * TTX - 1) / (4 * TTX);
+    g.nty = (g.ny + TTY - 1) / TTY;
+    g.zchunk = pick_zchunk_rounds(g.nz, (int64_t)g.ntx * g.nty,
+                                  launch_slots(reinterpret_cast<const void *>(&tti_kernel<R, TTX, TTY>),
+                                               TTX * TTY), 8, 128, 1);
+    g.nzc = (g.nz + g.zchunk - 1) / g.zchunk;
+    for (int k = 0; k <= R; ++k) a.c2w[k] = w->lap[k];
+    for (int k = 0; k < R; ++k) a.d1[k] = t->d1[k];
+    a.pc = pc + o;
+    a.qc = qc + o;
+    a.dzp = dzp + o;
+    a.dzq = dzq + o;
+    a.dzzp = dzzp + o;
+    a.dzzq = dzzq + o;
+    a.pp = pp + o;
+    a.qp = qp + o;
+    a.c2 = w->c2 + o;
+    a.eps = t->eps + o;
+    a.delta = t->delta + o;
+    a.theta = t->theta + o;
+    a.phi = t->phi + o;
+    a.c2s = w->c2_scale;
+    a.sigma = t->sigma;
+    a.alpha = t->alpha;
+    a.pn = pn + o;
+    a.qn = qn + o;
+    a.traces = w->traces ? w->traces + (int64_t)n * gd->ny * gd->nx : nullptr;
+    a.src = (w->src_dt2f && n >= 0 && n < w->nt) ? w->src_dt2f + n : nullptr;
+    a.src_z = (int)w->src_z;
+    a.src_y = (int)w->src_y;
+    a.src_x = (int)w->src_x;
+    a.sponge_w = w->sponge_width;
+    a.sponge_a = w->sponge_alpha;
+    a.faces = w->sponge_faces;
+    const int64_t nblk = (int64_t)g.ntx * g.nty * g.nzc;
+    if (nblk > 0x7fffffff) return MMS_EINVAL;
+    hipLaunchKernelGGL((tti_kernel<R, TTX, TTY>), dim3((unsigned)nblk), dim3(TTX * TTY), 0, s, a);
+    return check_launch("tti_kernel");
+}
+
+}  // namespace
+
+int tti_step(const mms_wave *w, const mms_tti *t, int n, const float *pp, const float *pc,
+             float *pn, const float *qp, const float *qc, float *qn, hipStream_t s) {
+    switch (w->radius) {
+        case 1: return launch_tti<1>(w, t, n, pp, pc, pn, qp, qc, qn, s);
+        case 2: return launch_tti<2>(w, t, n, pp, pc, pn, qp, qc, qn, s);
+        case 3: return launch_tti<3>(w, t, n, pp, pc, pn, qp, qc, qn, s);
+        case 4: return launch_tti<4>(w, t, n, pp, pc, pn, qp, qc, qn, s);
+        default: return MMS_EUNSUPPORTED;
+    }
+}
+
+}  // namespace mms

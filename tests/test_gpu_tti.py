@@ -1,0 +1,172 @@
+"""GPU parity of the pseudo-acoustic TTI step against the FP64 oracle.
+
+Gates as for the other steps: one step from identical FP32 inputs, normwise max
+error <= 1e-5; a multi-step run is gated at 1e-3 (numbers are printed).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.helpers import interior, rel_errors
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+LAP = [float(v) for v in synth.LAPLACIAN_R4]
+D1 = [float(v) for v in synth.FIRST_DERIV_R4]
+FACES = synth.SPONGE_LATERAL_AND_BOTTOM
+SIGMA = 0.1
+
+
+@pytest.fixture(scope="module")
+def mms():
+    import paper_2507_11067_amd as m
+    return m
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def smooth(seed, grid):
+    return synth.smooth_random_grid(seed, grid.nx, grid.ny, grid.nz)
+
+
+def medium(mms, nx, ny, nz, seed, nt):
+    """Layered C2 (Courant 0.4 / sqrt(1 + 2 eps_max)), Thomsen and tilt fields, source."""
+    grid = mms.Grid(nx, ny, nz)
+    v = synth.layered_velocity(nx, seed, nz=nz, ny=ny, sigma=2.0)
+    eps, delta = synth.thomsen_fields(nx, ny, nz, seed + 1, sy=grid.sy)
+    theta, phi = synth.tilt_fields(nx, ny, nz, seed + 2, sy=grid.sy)
+    dt = 0.4 * 10.0 / v.max() / np.sqrt(1 + 2 * float(eps.max()))
+    c2 = synth.padded_zeros(nx, ny, nz, sy=grid.sy)
+    synth.interior(c2, nx, ny, nz)[...] = ((v * dt / 10.0) ** 2).astype(np.float32)
+    f = (dt * dt * synth.ricker(nt, dt, 15.0) * 1e4).astype(np.float32)
+    src = (min(2, nz - 1), ny // 2, nx // 2)
+    return grid, c2, (eps, delta, theta, phi), f, src
+
+
+def gpu_tti(mms, grid, fields, sigma=SIGMA, alpha=1.0, d1=D1):
+    return mms.Tti(grid, *[T(a) for a in fields], sigma, alpha, d1)
+
+
+def oracle_tti(ow, fields, sigma=SIGMA, alpha=1.0, d1=D1):
+    return ow.tti(*fields, sigma, alpha, d1)
+
+
+@pytest.mark.parametrize("dims", [(20, 20, 20), (37, 19, 11), (300, 10, 21)],
+                         ids=lambda d: "x".join(map(str, d)))
+def test_tti_step_parity(mms, dims):
+    nx, ny, nz = dims
+    nt, n = 8, 3
+    grid, c2, fields, f, src = medium(mms, nx, ny, nz, 130, nt)
+    pp, pc, qp, qc = (smooth(131 + k, grid) for k in range(4))
+    traces = torch.zeros((nt, ny, nx), device=DEV)
+    w = mms.Wave(grid, T(c2), LAP, nt, 1.0, 4, 0.1, FACES, src, T(f), traces)
+    t = gpu_tti(mms, grid, fields)
+    pn, qn = grid.zeros(DEV), grid.zeros(DEV)
+    w.tti_step(n, t, T(pp), T(pc), pn, T(qp), T(qc), qn)
+    # in place: next = prev for both fields gives the same bits
+    ppt, qpt = T(pp), T(qp)
+    w2 = mms.Wave(grid, T(c2), LAP, nt, 1.0, 4, 0.1, FACES, src, T(f))
+    w2.tti_step(n, t, ppt, T(pc), ppt, qpt, T(qc), qpt)
+    torch.cuda.synchronize()
+    ow = oracle.Wave(nx, ny, nz, c2, LAP, src, f, nt, 4, 0.1, FACES)
+    rp, rq, tr = ow.tti_step(oracle_tti(ow, fields), n, pp, pc, qp, qc)
+    for name, got, ref in (("p", pn, rp), ("q", qn, rq)):
+        g = got.cpu().numpy()
+        rmax, rrms = rel_errors(interior(g, grid), interior(ref, grid))
+        print(f"TTI step {dims} {name}: rel_max {rmax:.2e} rel_rms {rrms:.2e}")
+        assert rmax <= 1e-5, (name, rmax, rrms)
+        assert np.count_nonzero(g) == np.count_nonzero(interior(g, grid))
+    assert torch.equal(ppt, pn) and torch.equal(qpt, qn)
+    np.testing.assert_array_equal(traces[n].cpu().numpy(), tr.astype(np.float32))
+    assert torch.count_nonzero(traces[:n]) == 0 and torch.count_nonzero(traces[n + 1:]) == 0
+
+
+@pytest.mark.parametrize("radius", [1, 2, 3])
+def test_tti_step_parity_short_radius(mms, radius):
+    nx, ny, nz = 45, 13, 17
+    nt, n = 4, 2
+    grid, c2, fields, f, src = medium(mms, nx, ny, nz, 140 + radius, nt)
+    rng = np.random.default_rng(radius)
+    lap = [float(v) for v in rng.uniform(-1, 1, radius + 1).astype(np.float32)]
+    d1 = [float(v) for v in rng.uniform(-1, 1, radius).astype(np.float32)]
+    pp, pc, qp, qc = (smooth(144 + k, grid) for k in range(4))
+    w = mms.Wave(grid, T(c2), lap, nt, 1.0, 0, 0.0, 0, src, T(f))
+    t = gpu_tti(mms, grid, fields, sigma=0.3, alpha=1.3, d1=d1)
+    pn, qn = grid.zeros(DEV), grid.zeros(DEV)
+    w.tti_step(n, t, T(pp), T(pc), pn, T(qp), T(qc), qn)
+    torch.cuda.synchronize()
+    ow = oracle.Wave(nx, ny, nz, c2, lap, src, f, nt)
+    rp, rq, _ = ow.tti_step(oracle_tti(ow, fields, 0.3, 1.3, d1), n, pp, pc, qp, qc)
+    for got, ref in ((pn, rp), (qn, rq)):
+        rmax, rrms = rel_errors(interior(got.cpu().numpy(), grid), interior(ref, grid))
+        assert rmax <= 1e-5, (radius, rmax, rrms)
+
+
+def test_tti_zero_tilt_equals_vti_kernel(mms):
+    """theta = 0, sigma = 0 and alpha = sqrt(1 + 2 delta) with constant delta: the TTI
+    kernel reproduces the VTI kernel."""
+    nx, ny, nz = 70, 33, 29
+    nt, n, d0 = 6, 4, 0.08
+    grid, c2, (eps, _, _, phi), f, src = medium(mms, nx, ny, nz, 150, nt)
+    delta = np.full(grid.shape, d0, np.float32)
+    zero = np.zeros(grid.shape, np.float32)
+    alpha = float(np.sqrt(np.float32(1 + 2 * d0)))
+    pp, pc, qp, qc = (T(smooth(151 + k, grid)) for k in range(4))
+    w = mms.Wave(grid, T(c2), LAP, nt, 1.0, 4, 0.1, FACES, src, T(f))
+    t = gpu_tti(mms, grid, (eps, delta, zero, phi), sigma=0.0, alpha=alpha)
+    pn, qn, hn, vn = (grid.zeros(DEV) for _ in range(4))
+    w.tti_step(n, t, pp, pc, pn, qp, qc, qn)
+    w.vti_step(n, T(1 + 2 * eps), T(np.sqrt(1 + 2 * delta)), pp, pc, hn, qp, qc, vn)
+    torch.cuda.synchronize()
+    for got, ref in ((pn, hn), (qn, vn)):
+        rmax, _ = rel_errors(interior(got.cpu().numpy(), grid), interior(ref.cpu().numpy(), grid))
+        assert rmax <= 2e-6, rmax
+
+
+def test_tti_forward_run_vs_oracle(mms):
+    """32^3, 200 steps from rest with the Ricker source, smooth tilt: p traces and the
+    final fields vs FP64."""
+    n, nt = 32, 200
+    grid, c2, fields, f, src = medium(mms, n, n, n, 160, nt)
+    traces = torch.zeros((nt, n, n), device=DEV)
+    w = mms.Wave(grid, T(c2), LAP, nt, 1.0, 8, 0.015, FACES, src, T(f), traces)
+    t = gpu_tti(mms, grid, fields)
+    P = [grid.zeros(DEV) for _ in range(2)]
+    Q = [grid.zeros(DEV) for _ in range(2)]
+    w.record(0, P[0])
+    for k in range(1, nt):
+        w.tti_step(k, t, P[(k - 1) % 2], P[k % 2], P[(k + 1) % 2],
+                   Q[(k - 1) % 2], Q[k % 2], Q[(k + 1) % 2])
+    torch.cuda.synchronize()
+    ow = oracle.Wave(n, n, n, c2, LAP, src, f, nt, 8, 0.015, FACES)
+    z = ow.zeros()
+    res = ow.tti_forward(oracle_tti(ow, fields), z, z, z, z)
+    rmax, rrms = rel_errors(traces.cpu().numpy(), res["traces"])
+    rP, _ = rel_errors(interior(P[nt % 2].cpu().numpy(), grid), interior(res["last"][1], grid))
+    rQ, _ = rel_errors(interior(Q[nt % 2].cpu().numpy(), grid), interior(res["last"][3], grid))
+    print(f"TTI 32^3 x {nt}: traces rel_max {rmax:.2e} rel_rms {rrms:.2e}; p {rP:.2e} q {rQ:.2e}")
+    assert rmax <= 1e-3 and rP <= 1e-3 and rQ <= 1e-3
+    assert np.abs(res["traces"]).max() > 0
+
+
+def test_tti_rejects_bad_arguments(mms):
+    grid, c2, fields, f, src = medium(mms, 12, 10, 9, 170, 4)
+    w = mms.Wave(grid, T(c2), LAP, 4, 1.0, 0, 0.0, 0, src, T(f))
+    t = gpu_tti(mms, grid, fields)
+    fs = [T(smooth(171 + k, grid)) for k in range(4)]
+    out = [grid.zeros(DEV) for _ in range(2)]
+    with pytest.raises(mms.MmsError):
+        w.tti_step(0, t, fs[0], fs[1], out[0], fs[2], fs[3], out[1])
+    with pytest.raises(mms.MmsError):     # output aliases the current level
+        w.tti_step(1, t, fs[0], fs[1], fs[1], fs[2], fs[3], out[1])
+    with pytest.raises(mms.MmsError):     # both outputs in one buffer
+        w.tti_step(1, t, fs[0], fs[1], out[0], fs[2], fs[3], out[0])
+    with pytest.raises(mms.MmsError):     # output inside the workspace
+        w.tti_step(1, t, fs[0], fs[1], t.work[0], fs[2], fs[3], out[1])
+    bad = gpu_tti(mms, grid, fields, alpha=0.0)
+    with pytest.raises(mms.MmsError):
+        w.tti_step(1, bad, fs[0], fs[1], out[0], fs[2], fs[3], out[1])
