@@ -17,6 +17,7 @@ Besides the headline the same JSON line carries, each measured in this run:
   * "table1": every kernel of the paper's Table I at 512^3 (the 2-D ones on each
     plane of the 512^3 stack), with HBM and FP32-FMA roofline fractions;
   * "vti": the 400^3, 1000-step pseudo-acoustic VTI forward model (two fields);
+  * "tti": the 400^3, 300-step pseudo-acoustic TTI forward model (two fields, tilt);
   * "gradient": the 256^3, 1000-step adjoint gradient with checkpointing,
     with its dot-product test;
   * "roofline" of the dominant kernel and "cpu_baseline" (the FP64 oracle on
@@ -57,9 +58,9 @@ def parse():
     p.add_argument("--n", type=int, default=512, help="headline grid edge")
     p.add_argument("--only", default="", help="profile one kernel: star|box2|box4|box4_bf16x3|"
                    "box4_fp16x3s|box3_bf16x3|wave|vti|copy|2DStarR2|2DStarR4|2DBoxR2|2DBoxR3|"
-                   "3DStarR2|3DBoxR1")
+                   "3DStarR2|3DBoxR1|tti")
     p.add_argument("--skip", default="", help="comma list of extras to skip: "
-                   "split,table1,rtm,vti,gradient,cpu,check")
+                   "split,table1,rtm,vti,tti,gradient,cpu,check")
     p.add_argument("--cpu-planes", type=int, default=0, help="oracle sample depth (0 = full grid)")
     p.add_argument("--collect", action="store_true",
                    help="run rocprofv3 (kernel trace, FETCH_SIZE, WRITE_SIZE) as child processes "
@@ -256,6 +257,8 @@ def main():
         result["rtm"] = bench_rtm(torch, mms, synth, dev)
     if "vti" not in skip:
         result["vti"] = bench_vti(torch, mms, synth, dev)
+    if "tti" not in skip:
+        result["tti"] = bench_tti(torch, mms, synth, dev)
     if "gradient" not in skip:
         result["gradient"] = bench_gradient(torch, mms, synth, dev)
     if "cpu" not in skip:
@@ -425,6 +428,53 @@ def bench_vti(torch, mms, synth, dev, n=400, nt=1000):
            "trace_max_abs": float(traces.abs().max().item()),
            "finite": bool(torch.isfinite(H[nt % 2]).all().item())}
     log(f"[bench] vti: {gpts:.1f} Gpoints/s ({ms:.0f} ms, {gpts * bpp:.0f} GB/s)")
+    return res
+
+
+TTI_SIGMA = 0.1   # v_sz^2 / v_pz^2: keeps the pseudo-acoustic pair stable under varying tilt
+
+
+def tti_problem(torch, mms, synth, dev, n, nt, seed=11):
+    """400^3 TTI medium: layered velocity, Thomsen fields, smooth tilt (0..45 deg) and
+    azimuth; C2 scaled by 1/(1 + 2 eps_max)."""
+    s = synth.wave_setup(n, nt, seed=seed, sponge_width=32)
+    grid = mms.Grid(n, n, n)
+    eps, delta = synth.thomsen_fields(n, n, n, seed + 1, sy=grid.sy)
+    theta, phi = synth.tilt_fields(n, n, n, seed + 2, sy=grid.sy)
+    shrink = 1.0 / (1.0 + 2.0 * float(eps.max()))
+    t = mms.Tti(grid, *[torch.from_numpy(a).to(dev) for a in (eps, delta, theta, phi)],
+                TTI_SIGMA, 1.0, [float(v) for v in synth.FIRST_DERIV_R4])
+    w = mms.Wave(grid, torch.from_numpy(s.c2).to(dev), LAP, nt, shrink, s.sponge_width,
+                 s.sponge_alpha, s.sponge_faces, s.src, torch.from_numpy(s.src_dt2f).to(dev))
+    return s, grid, w, t
+
+
+def bench_tti(torch, mms, synth, dev, n=400, nt=300):
+    """Pseudo-acoustic TTI forward model, 400^3, 300 steps, p traces recorded."""
+    log(f"[bench] tti setup {n}^3 x {nt}")
+    s, grid, w, t = tti_problem(torch, mms, synth, dev, n, nt)
+    traces = torch.zeros((nt, n, n), device=dev)
+    w.set_traces(traces)
+    P = [grid.zeros(dev) for _ in range(2)]
+    Q = [grid.zeros(dev) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    w.record(0, P[0])
+    for k in range(1, nt):
+        w.tti_step(k, t, P[(k - 1) % 2], P[k % 2], P[(k + 1) % 2],
+                   Q[(k - 1) % 2], Q[k % 2], Q[(k + 1) % 2])
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    gpts = grid.points * (nt - 1) / (ms * 1e-3) / 1e9
+    bpp = 44.0      # fused minimum: p, q at n and n-1, C2, eps, delta, theta, phi; p, q out
+    res = {"grid": [n, n, n], "steps": nt - 1, "ms_total": ms, "ms_per_step": ms / (nt - 1),
+           "gpoints_s": gpts, "gbs": gpts * bpp, "hbm_frac": gpts * bpp / HBM_PEAK_GBS,
+           "algorithmic_bytes_per_point": bpp, "two_pass_bytes_per_point": 84.0,
+           "sigma": TTI_SIGMA, "trace_max_abs": float(traces.abs().max().item()),
+           "finite": bool(torch.isfinite(P[nt % 2]).all().item())}
+    log(f"[bench] tti: {gpts:.1f} Gpoints/s ({ms:.0f} ms, {gpts * bpp:.0f} GB/s at 44 B/pt)")
     return res
 
 
@@ -615,8 +665,12 @@ COUNTED = {
     "box3_bf16x3": ("box_mfma.hip", "box_mfma_kernel<3, 1>", 8.0),
     "wave": ("wave.hip", "wave_kernel<4, 0, false", 16.0),   # 400^3 forward step, no image
     "vti": ("vti.hip", "vti_kernel<4", 36.0),                # 400^3 VTI step
+    "tti_dz": ("tti.hip", "tti_dz_kernel<4", 24.0),          # 400^3 TTI pass 1 (padded rows)
+    "tti": ("tti.hip", "tti_kernel<4", 60.0),                # 400^3 TTI pass 2
 }
-COUNTED_POINTS = {"wave": 400 ** 3, "vti": 400 ** 3}
+COUNTED_POINTS = {"wave": 400 ** 3, "vti": 400 ** 3, "tti_dz": 400 ** 3, "tti": 400 ** 3}
+# the --only command that launches each counted kernel
+COUNTED_ONLY = {"tti_dz": "tti"}
 
 
 def source_sha(fname):
@@ -726,9 +780,10 @@ def collect_counters(args):
         summary["trace_headline"][name] = {"avg_ns": ns, "calls": calls}
     # 1b. kernel traces of the single-kernel commands (split MFMA boxes, wave, VTI)
     summary["trace_only"] = {}
-    for name in ("box4_bf16x3", "box3_bf16x3", "wave", "vti"):
+    for name in ("box4_bf16x3", "box3_bf16x3", "wave", "vti", "tti_dz", "tti"):
         d, cmd = prof(f"trace_{name}", ["--kernel-trace", "--stats"],
-                      ["--only", name, "--steps", "20", "--warmup", "2"], 120)
+                      ["--only", COUNTED_ONLY.get(name, name), "--steps", "20", "--warmup", "2"],
+                      120)
         ns, calls = _stats_mean_ns(find(d, "_kernel_stats.csv"), COUNTED[name][1])
         summary["trace_only"][name] = {"avg_ns": ns, "calls": calls, "command": cmd,
                                        "source_sha": source_sha(COUNTED[name][0])}
@@ -739,7 +794,8 @@ def collect_counters(args):
     for name, (src, sym, bpp) in COUNTED.items():
         e = {"source": src, "source_sha": source_sha(src), "symbol": sym}
         for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
-            d, cmd = prof(f"{name}_{ctr}", ["--pmc", ctr], ["--only", name, "--steps", "3",
+            d, cmd = prof(f"{name}_{ctr}", ["--pmc", ctr], ["--only", COUNTED_ONLY.get(name, name),
+                                                             "--steps", "3",
                                                              "--warmup", "1"], 90)
             kib, cnt = _counter_mean(find(d, "_counter_collection.csv"), sym)
             e[ctr.lower() + "_kib"] = kib
@@ -820,6 +876,17 @@ def profile_only(args, torch, mms, synth, grid, x, outs, sweeps, c_box4, c_box3,
     elif k in table1_kernels(synth):
         shape, r, c, _ = table1_kernels(synth)[k]
         f = lambda: mms.stencil_apply(x, out, grid, shape, r, c)
+    elif k == "tti":
+        _, g4, wt, tt = tti_problem(torch, mms, synth, dev, 400, 64)
+        P = [g4.zeros(dev) for _ in range(2)]
+        Q = [g4.zeros(dev) for _ in range(2)]
+        it = [0]
+
+        def f():
+            i = it[0] % 60 + 1
+            wt.tti_step(i, tt, P[(i - 1) % 2], P[i % 2], P[(i + 1) % 2],
+                        Q[(i - 1) % 2], Q[i % 2], Q[(i + 1) % 2])
+            it[0] += 1
     elif k == "vti":
         n = 400
         s, g4, ta, tb, c2, fsrc, shrink = vti_problem(torch, mms, synth, dev, n, 64)

@@ -1,7 +1,8 @@
 """Parity at the workloads' full sizes, in the launch configuration bench.py times:
 one acoustic step at 400^3 (with receivers and the FP64 image), the first 40
-RTM steps at 400^3 from rest, one adjoint step with gradient at 256^3, and one
-VTI step at 400^3 -- every output point against the FP64 oracle.
+RTM steps at 400^3 from rest, one adjoint step with gradient at 256^3, one VTI
+step at 400^3 -- every output point against the FP64 oracle -- and one TTI step
+at 400^3 on its top planes.
 
 Gates: one step from identical FP32 inputs, normwise max error <= 1e-5; the
 40-step run accumulates rounding and is gated at 1e-4 (numbers are printed).
@@ -133,5 +134,41 @@ def test_vti_step_400(mms, rtm400):
     for name, got, ref in (("H", hn, rh), ("V", vn, rv)):
         rmax, rrms = rel_errors(interior(got.cpu().numpy(), grid), interior(ref, grid))
         print(f"VTI step 400^3 {name}: rel_max {rmax:.2e} rel_rms {rrms:.2e}")
+        assert rmax <= 1e-5, (name, rmax, rrms)
+    np.testing.assert_array_equal(traces[k].cpu().numpy(), tr.astype(np.float32))
+
+
+def test_tti_step_400_top_slab(mms, rtm400):
+    """One TTI step at 400^3 in the benchmark's configuration, checked on the top 24
+    planes (receivers and source included) against the oracle run on the top 28
+    planes: those outputs read only planes < 28, and the bottom sponge does not reach
+    them (W = 32 from z = 399), so the slab sees the same operands."""
+    s = rtm400
+    n, nt, k, zs = 400, s.nt, 6, 28
+    grid = mms.Grid(n, n, n)
+    eps, delta = synth.thomsen_fields(n, n, n, 12, sy=grid.sy)
+    theta, phi = synth.tilt_fields(n, n, n, 13, sy=grid.sy)
+    shrink = 1.0 / (1.0 + 2.0 * float(eps.max()))
+    d1 = [float(v) for v in synth.FIRST_DERIV_R4]
+    fields = [uniform(101 + i, n) for i in range(4)]
+    traces = torch.zeros((nt, n, n), device=DEV)
+    w = mms.Wave(grid, T(s.c2), LAP, nt, shrink, s.sponge_width, s.sponge_alpha, s.sponge_faces,
+                 s.src, T(s.src_dt2f), traces)
+    t = mms.Tti(grid, T(eps), T(delta), T(theta), T(phi), 0.1, 1.0, d1)
+    pn, qn = grid.zeros(DEV), grid.zeros(DEV)
+    w.tti_step(k, t, *[T(a) for a in fields[:2]], pn, *[T(a) for a in fields[2:]], qn)
+    torch.cuda.synchronize()
+    top = lambda a: np.ascontiguousarray(a[:zs + 8])     # planes -4 .. zs+3 of the padded array
+    c2s = (np.float32(shrink) * s.c2).astype(np.float32)
+    ow = oracle.Wave(n, n, zs, top(c2s), LAP, s.src, s.src_dt2f, nt, s.sponge_width,
+                     s.sponge_alpha, s.sponge_faces & ~32)      # no bottom face in the slab
+    tt = ow.tti(top(eps), top(delta), top(theta), top(phi), 0.1, 1.0, d1)
+    rp, rq, tr = ow.tti_step(tt, k, *[top(a) for a in fields])
+    H = 4
+    for name, got, ref in (("p", pn, rp), ("q", qn, rq)):
+        g = got.cpu().numpy()[H:H + 24, H:H + n, H:H + n]
+        r = ref[H:H + 24, H:H + n, H:H + n]
+        rmax, rrms = rel_errors(g, r)
+        print(f"TTI step 400^3 top planes {name}: rel_max {rmax:.2e} rel_rms {rrms:.2e}")
         assert rmax <= 1e-5, (name, rmax, rrms)
     np.testing.assert_array_equal(traces[k].cpu().numpy(), tr.astype(np.float32))
