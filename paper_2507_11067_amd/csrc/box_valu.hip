@@ -17,6 +17,8 @@
 //    words) and applies all (2r+1) x (2r+1) weights of that dy to them, so LDS
 //    traffic is 3 words per (2r+1)^2 * 4 FMAs; the weights are uniform and come
 //    from the kernel-argument segment through the scalar unit.
+#include <type_traits>
+
 #include "mms_internal.h"
 
 namespace mms {
@@ -95,25 +97,39 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
         const bool more = zi + 1 < z_last;
         if (more) load_plane(zi + 1);
         const float4 *t = &tile[buf][0][0];
-        for (int dy = -R; dy <= R; ++dy) {
-            const float4 *row = t + (ty + R + dy) * LW4;
-            const float4 L = row[tx], C = row[tx + 1], Rr = row[tx + 2];
-            const float w[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w, Rr.x, Rr.y, Rr.z, Rr.w};
-            const float *cdy = a.c + (dy + R) * W;
+        // Input planes within r of the chunk's ends feed some output planes outside
+        // it; those (dz) terms are skipped there.  Every other plane feeds all 2r+1
+        // accumulators, and that path has no per-dz test.
+        auto plane = [&](auto checked) {
+            // dy stays a loop: unrolled, its (2r+1)^3 weights would all be hoisted
+            // into scalar registers and spill to vector-register lanes
+#pragma unroll 1
+            for (int dy = -R; dy <= R; ++dy) {
+                const float4 *row = t + (ty + R + dy) * LW4;
+                const float4 L = row[tx], C = row[tx + 1], Rr = row[tx + 2];
+                const float w[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w, Rr.x, Rr.y, Rr.z, Rr.w};
+                const float *cdy = a.c + (dy + R) * W;
 #pragma unroll
-            for (int dz = -R; dz <= R; ++dz) {
-                const int zo = zi - dz;  // output plane fed through c[dz]
-                if (zo < zb || zo >= ze) continue;
-                const float *cc = cdy + (dz + R) * W * W;
+                for (int dz = -R; dz <= R; ++dz) {
+                    if (decltype(checked)::value) {
+                        const int zo = zi - dz;  // output plane fed through c[dz]
+                        if (zo < zb || zo >= ze) continue;
+                    }
+                    const float *cc = cdy + (dz + R) * W * W;
 #pragma unroll
-                for (int dx = -R; dx <= R; ++dx) {
-                    const float ck = cc[dx + R];
+                    for (int dx = -R; dx <= R; ++dx) {
+                        const float ck = cc[dx + R];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        acc[R - dz][e] = fmaf(ck, w[4 + e + dx], acc[R - dz][e]);
+                        for (int e = 0; e < 4; ++e)
+                            acc[R - dz][e] = fmaf(ck, w[4 + e + dx], acc[R - dz][e]);
+                    }
                 }
             }
-        }
+        };
+        if (zi >= zb + R && zi < ze - R)
+            plane(std::false_type{});
+        else
+            plane(std::true_type{});
         // output plane zi - R is complete
         const int zo = zi - R;
         if (zo >= zb && y < g.ny && x0 < g.nx) {
@@ -161,6 +177,9 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
         const int64_t cols = (int64_t)g.ntx * g.nty;
         zc = (int)((int64_t)g.nz * cols / 4096);
         zc = zc < 16 ? 16 : zc;
+        // radius 1 is bound by HBM: long chunks cut the re-read halo planes
+        // (measured at 512^3: 512 Gpoints/s at 128 planes against 441 at 32)
+        if (R == 1) zc = 128;
     }
     g.zchunk = zc;
     g.nzc = (g.nz + zc - 1) / zc;

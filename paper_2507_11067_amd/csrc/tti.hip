@@ -16,8 +16,8 @@
 //    so a lane owns one 16-byte word of it and the loads are fully coalesced.
 //  * pass 2 (x and y): per plane, the tiles of p, q, Dz p and Dz q with r rows
 //    and 4 cells of halo are staged in a double-buffered LDS tile (the next
-//    plane's tiles are fetched after the current plane's arithmetic, so that no
-//    registers stay reserved for them); Dxx, Dyy and Dxy = Dx(Dy f) come from the p / q tiles, Dxz =
+//    plane's tiles are requested after the current plane's derivatives, so that
+//    no registers stay reserved for them across that phase); Dxx, Dyy and Dxy = Dx(Dy f) come from the p / q tiles, Dxz =
 //    Dx(Dz f) and Dyz = Dy(Dz f) from the Dz tiles; the direction cosines come
 //    from theta / phi per cell; the update is fused with the sponge, source and
 //    receivers; outputs are written with streaming stores.
@@ -268,80 +268,75 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
             cf[5][e] = 2.f * nx_ * nz_;
         }
 
-        // x/y parts of L f and H1 f for both fields: [field][e]
-        float lxy[2][4], h1[2][4];
+        // x/y parts of L f and H1 f for both fields: [field][e].  Rows y+k and y-k are
+        // taken together (they share the weights d_k and c_k); k runs as a loop so
+        // that only one pair of rows per field is in registers at a time.
+        float sxx[2][4], syy[2][4], sxy[2][4], sxz[2][4], syz[2][4];
+        auto window = [&](const float4 *row, float *w) {
+            const float4 L = row[0], C = row[1], Rr = row[2];
+            w[0] = L.x; w[1] = L.y; w[2] = L.z; w[3] = L.w;
+            w[4] = C.x; w[5] = C.y; w[6] = C.z; w[7] = C.w;
+            w[8] = Rr.x; w[9] = Rr.y; w[10] = Rr.z; w[11] = Rr.w;
+        };
+        auto dx1 = [&](const float *w, int e) {   // first x derivative at cell e
+            float d = 0.f;
+#pragma unroll
+            for (int j = 1; j <= R; ++j) d = fmaf(a.d1[j - 1], w[4 + e + j] - w[4 + e - j], d);
+            return d;
+        };
 #pragma unroll
         for (int fi = 0; fi < 2; ++fi) {
-            // one field at a time: stops the scheduler from hoisting every LDS read
-            __builtin_amdgcn_sched_barrier(0);
-            const float4 *t = &tile[buf][fi][0][0] + ty * LW4 + tx;  // window row 0 = y - R
-            float syy[4], sxy[4] = {0.f, 0.f, 0.f, 0.f}, sxx[4];
-            // rows one at a time: unrolling lets the scheduler hoist every row's LDS
-            // words at once, far beyond the register file
-#pragma unroll 1
-            for (int i = 0; i <= 2 * R; ++i) {
-                const int k = i - R;
-                const float4 L = t[i * LW4], C = t[i * LW4 + 1], Rr = t[i * LW4 + 2];
-                const float w[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w, Rr.x, Rr.y, Rr.z, Rr.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    if (k == 0) {
-                        float s2 = a.c2w[0] * w[4 + e];
-#pragma unroll
-                        for (int j = 1; j <= R; ++j) s2 = fmaf(a.c2w[j], w[4 + e + j] + w[4 + e - j], s2);
-                        sxx[e] = s2;
-                        syy[e] = a.c2w[0] * w[4 + e];
-                    } else {
-                        float dx = 0.f;
-#pragma unroll
-                        for (int j = 1; j <= R; ++j) dx = fmaf(a.d1[j - 1], w[4 + e + j] - w[4 + e - j], dx);
-                        const float dk = k > 0 ? a.d1[k - 1] : -a.d1[-k - 1];
-                        sxy[e] = fmaf(dk, dx, sxy[e]);
-                    }
-                }
-            }
-            // y second derivative from the centre words of the window rows
-#pragma unroll
-            for (int k = 1; k <= R; ++k) {
-                const float4 u = t[(R + k) * LW4 + 1], d = t[(R - k) * LW4 + 1];
-                syy[0] = fmaf(a.c2w[k], u.x + d.x, syy[0]);
-                syy[1] = fmaf(a.c2w[k], u.y + d.y, syy[1]);
-                syy[2] = fmaf(a.c2w[k], u.z + d.z, syy[2]);
-                syy[3] = fmaf(a.c2w[k], u.w + d.w, syy[3]);
-            }
-            // Dz tile: x window of the centre row (Dxz), y column of the centre word (Dyz)
-            __builtin_amdgcn_sched_barrier(0);
+            const float4 *t = &tile[buf][fi][0][0] + ty * LW4 + tx;      // row 0 = y - R
             const float4 *tz = &tile[buf][2 + fi][0][0] + ty * LW4 + tx;
-            float sxz[4], syz[4] = {0.f, 0.f, 0.f, 0.f};
-            {
-                const float4 L = tz[R * LW4], C = tz[R * LW4 + 1], Rr = tz[R * LW4 + 2];
-                const float w[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w, Rr.x, Rr.y, Rr.z, Rr.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    float s1 = 0.f;
-#pragma unroll
-                    for (int j = 1; j <= R; ++j) s1 = fmaf(a.d1[j - 1], w[4 + e + j] - w[4 + e - j], s1);
-                    sxz[e] = s1;
-                }
-            }
-#pragma unroll
-            for (int j = 1; j <= R; ++j) {
-                const float4 u = tz[(R + j) * LW4 + 1], d = tz[(R - j) * LW4 + 1];
-                const float dj = a.d1[j - 1];
-                syz[0] = fmaf(dj, u.x - d.x, syz[0]);
-                syz[1] = fmaf(dj, u.y - d.y, syz[1]);
-                syz[2] = fmaf(dj, u.z - d.z, syz[2]);
-                syz[3] = fmaf(dj, u.w - d.w, syz[3]);
-            }
+            float w[12], wz[12];
+            window(t + R * LW4, w);
+            window(tz + R * LW4, wz);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                lxy[fi][e] = sxx[e] + syy[e];
-                h1[fi][e] = cf[0][e] * sxx[e] + cf[1][e] * syy[e] + cf[3][e] * sxy[e] +
-                            cf[4][e] * syz[e] + cf[5][e] * sxz[e];
+                float s2 = a.c2w[0] * w[4 + e];
+#pragma unroll
+                for (int j = 1; j <= R; ++j) s2 = fmaf(a.c2w[j], w[4 + e + j] + w[4 + e - j], s2);
+                sxx[fi][e] = s2;
+                syy[fi][e] = a.c2w[0] * w[4 + e];
+                sxy[fi][e] = 0.f;
+                sxz[fi][e] = dx1(wz, e);
+                syz[fi][e] = 0.f;
             }
         }
-        // keep the point-wise loads below the derivative phase (register pressure)
+#pragma unroll 1
+        for (int k = 1; k <= R; ++k) {
+            const float dk = a.d1[k - 1], ck = a.c2w[k];
+#pragma unroll
+            for (int fi = 0; fi < 2; ++fi) {
+                const float4 *t = &tile[buf][fi][0][0] + ty * LW4 + tx;
+                const float4 *tz = &tile[buf][2 + fi][0][0] + ty * LW4 + tx;
+                float wu[12], wd[12];
+                window(t + (R + k) * LW4, wu);
+                window(t + (R - k) * LW4, wd);
+                const float4 zu = tz[(R + k) * LW4 + 1], zd = tz[(R - k) * LW4 + 1];
+                const float zuv[4] = {zu.x, zu.y, zu.z, zu.w}, zdv[4] = {zd.x, zd.y, zd.z, zd.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    sxy[fi][e] = fmaf(dk, dx1(wu, e) - dx1(wd, e), sxy[fi][e]);
+                    syy[fi][e] = fmaf(ck, wu[4 + e] + wd[4 + e], syy[fi][e]);
+                    syz[fi][e] = fmaf(dk, zuv[e] - zdv[e], syz[fi][e]);
+                }
+            }
+        }
+        float lxy[2][4], h1[2][4];
+#pragma unroll
+        for (int fi = 0; fi < 2; ++fi)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                lxy[fi][e] = sxx[fi][e] + syy[fi][e];
+                h1[fi][e] = cf[0][e] * sxx[fi][e] + cf[1][e] * syy[fi][e] + cf[3][e] * sxy[fi][e] +
+                            cf[4][e] * syz[fi][e] + cf[5][e] * sxz[fi][e];
+            }
+        // keep the loads below the derivative phase (register pressure): the next
+        // plane's tiles are requested here, so their latency overlaps this plane's
+        // point-wise loads, update and stores
         __builtin_amdgcn_sched_barrier(0);
+        if (more) load_tiles(z + 1, tw);
         float4 ow[NOWN];
 #pragma unroll
         for (int f = 0; f < NOWN - 2; ++f) ow[f] = select_load(osrc[f] + zo + own_off, own_ok, a.c2);
@@ -401,13 +396,7 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
                     if (x0 + e < g.nx) pt[e] = pcv[e];
             }
         }
-        if (more) {
-            // next plane's tiles into the other buffer; the loads are issued after the
-            // compute so that no register stays reserved for them across it (other
-            // waves cover their latency)
-            load_tiles(z + 1, tw);
-            tile_store(buf ^ 1, tw);
-        }
+        if (more) tile_store(buf ^ 1, tw);
         __syncthreads();
     }
 }
