@@ -661,8 +661,8 @@ COUNTED = {
     "star": ("star.hip", "star_kernel<4", 8.0),
     "box2": ("box_valu.hip", "box_valu_kernel<2", 8.0),
     "box4": ("box_valu.hip", "box_valu_kernel<4", 8.0),
-    "box4_bf16x3": ("box_mfma.hip", "box_mfma_kernel<4, 1>", 8.0),
-    "box3_bf16x3": ("box_mfma.hip", "box_mfma_kernel<3, 1>", 8.0),
+    "box4_bf16x3": ("box_mfma.hip", "box_mfma_kernel<4, 1,", 8.0),
+    "box3_bf16x3": ("box_mfma.hip", "box_mfma_kernel<3, 1,", 8.0),
     "wave": ("wave.hip", "wave_kernel<4, 0, false", 16.0),   # 400^3 forward step, no image
     "vti": ("vti.hip", "vti_kernel<4", 36.0),                # 400^3 VTI step
     "tti_dz": ("tti.hip", "tti_dz_kernel<4", 24.0),          # 400^3 TTI pass 1 (padded rows)
