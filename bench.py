@@ -557,13 +557,18 @@ def gradient_checks(torch, mms, synth, prob, m, d_obs, grid, dev, npts=16, seed=
     mi = grid.interior(m.detach()).cpu().numpy()
     rng = np.random.default_rng(seed)
     # points from the top decile of the gradient smoothed at the bump's width, away from
-    # the faces, so that the directional derivative <g, bump> is well above rounding
+    # the faces, and within two decades of its largest value: the gradient spans many
+    # decades (it falls off with distance from source and receivers), and a directional
+    # derivative <g, bump> far below the largest one sits at the rounding level of the
+    # FP32 traces, where no finite difference can resolve it
     from scipy.ndimage import gaussian_filter
     gs = np.abs(gaussian_filter(gi.astype(np.float64), sigma=2.0, truncate=3.0))
     core = np.zeros_like(gs, dtype=bool)
     core[6:-6, 6:-6, 6:-6] = True
-    cut = np.quantile(gs[core], 0.9)
+    cut = max(np.quantile(gs[core], 0.9), 1e-2 * float(gs[core].max()))
     cand = np.argwhere(core & (gs >= cut))
+    if len(cand) < npts:
+        cand = np.argwhere(core & (gs >= np.sort(gs[core])[-npts]))
     pick = cand[rng.choice(len(cand), npts, replace=False)]
     md = m.detach()
     # (a) one cell per point: in FP32 the trace change of a single-cell perturbation sits
@@ -605,11 +610,13 @@ def gradient_checks(torch, mms, synth, prob, m, d_obs, grid, dev, npts=16, seed=
         fd_rows.append(row)
     cr = [r["cell_rel"] for r in fd_rows]
     br = [r["bump_rel"] for r in fd_rows]
-    fdres = {"points": fd_rows, "cell_eps_rel": 5e-2, "bump_sigma_cells": sig,
+    fdres = {"points": fd_rows, "selection": "top decile of |smoothed g| and >= 1e-2 of its max",
+             "cell_eps_rel": 5e-2, "bump_sigma_cells": sig,
              "bump_amp_rel": 1e-2, "cell_rel_median": float(np.median(cr)),
              "cell_rel_max": float(np.max(cr)), "bump_rel_median": float(np.median(br)),
-             "bump_rel_max": float(np.max(br))}
-    log(f"[bench] FD at 16 top-decile points: single cell rel median {fdres['cell_rel_median']:.2e}"
+             "bump_rel_max": float(np.max(br)), "bump_gate": 5e-2,
+             "bump_pass": bool(np.max(br) <= 5e-2)}
+    log(f"[bench] FD at 16 points of large gradient: single cell rel median {fdres['cell_rel_median']:.2e}"
         f" max {fdres['cell_rel_max']:.2e}; bump rel median {fdres['bump_rel_median']:.2e} "
         f"max {fdres['bump_rel_max']:.2e}")
     # Taylor test along a smooth direction dm (max |dm| = 1 % of mean m)
