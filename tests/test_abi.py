@@ -80,6 +80,8 @@ def test_stencil_apply_validation(L):
     assert apply(L, grid(sy=20)) == EINVAL                  # pitch too small
     assert apply(L, grid(sz=24 * 23)) == EINVAL             # plane stride too small
     assert apply(L, grid(nx=-1)) == EINVAL
+    assert apply(L, grid(nx=2 ** 30 + 1)) == EINVAL         # beyond 2^30 cells per axis
+    assert apply(L, grid(nz=2 ** 30 + 1)) == EINVAL
     assert apply(L, grid(), out=ctypes.c_void_p(0x10008)) == EINVAL  # misaligned / overlapping
     assert apply(L, grid(), out=ctypes.c_void_p(0x10010)) == EINVAL  # overlapping
 
