@@ -15,7 +15,7 @@ SOURCES = ["abi.hip", "star.hip", "box_valu.hip", "box_mfma.hip", "plane2d.hip",
            "vti.hip", "tti.hip", "reduce.hip"]
 
 # Packed FP32 instructions stay off: only scalar FP32 FMAs are emitted.
-HIPFLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-I" + INCLUDE,
+HIPFLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++20", "-fPIC", "-I" + INCLUDE,
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-Wall", "-Wno-unused-function"]
 
