@@ -777,7 +777,7 @@ def collect_counters(args):
 
     summary = {"kernels": {}, "commands": {}}
     # 1. kernel trace of the headline command
-    targs = ["--steps", "20", "--warmup", "2", "--skip", "split,rtm,gradient,cpu,check"]
+    targs = ["--steps", "20", "--warmup", "2", "--skip", "split,table1,rtm,vti,tti,gradient,cpu,check"]
     d, cmd = prof("trace_headline", ["--kernel-trace", "--stats"], targs, 300)
     stats = find(d, "_kernel_stats.csv")
     summary["commands"]["trace_headline"] = cmd
