@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define MMS_ABI_VERSION 1
+#define MMS_ABI_VERSION 2
 
 /* error codes */
 #define MMS_OK 0
@@ -109,12 +109,21 @@ typedef struct mms_wave {
     const float *src_dt2f;/* device [nt]: dt^2 f(n dt), or NULL for no source       */
     float *traces;        /* device [nt][ny][nx]: d^n = u^n(z = 0), or NULL          */
     double *image;        /* device [nz][ny][nx] FP64: += (u^{n+1})^2, or NULL       */
+    float *image_part;    /* device [nz][ny][nx] FP32 workspace for image_block > 1  */
+    int32_t image_block;  /* K: 0 or 1 adds every step's term to image in FP64; K > 1 */
+                          /* sums the terms of K consecutive steps (n = 1+jK .. (j+1)K)*/
+                          /* in FP32 in image_part and adds that sum to image at the   */
+                          /* block's last step and at step nt-1                        */
+    int32_t pad_;         /* unused, keep 0                                          */
 } mms_wave;
 
 /*
  * mms_wave_step -- one forward step n (1 <= n < nt): u_next = u^{n+1} from
  * u_prev = u^{n-1}, u_cur = u^n; records traces[n] = u^n(z = 0) and adds
- * (u^{n+1})^2 to image when those are set.  u_next may equal u_prev (the update
+ * (u^{n+1})^2 to image when those are set.  With image_block = K > 1 the image holds
+ * every term of steps 1..n once n is a multiple of K or n = nt-1 (each block of K
+ * steps is summed in FP32, relative error <= K 2^-24, and added in FP64); the steps of
+ * a block must run in order.  u_next may equal u_prev (the update
  * reads and writes each cell in place); u_next must not overlap u_cur.
  */
 int mms_wave_step(const mms_wave *w, int n, const float *u_prev, const float *u_cur,

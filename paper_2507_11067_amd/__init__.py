@@ -143,9 +143,15 @@ class Wave:
         self._w.traces = _dev_ptr(traces, "traces", torch.float32,
                                   self.nt * self.grid.ny * self.grid.nx)
 
-    def set_image(self, image: torch.Tensor | None):
+    def set_image(self, image: torch.Tensor | None, part: torch.Tensor | None = None,
+                  block: int = 1):
+        """FP64 image; with block K > 1 the terms of K consecutive steps are summed in the
+        FP32 workspace `part` ([nz, ny, nx]) and added to the image at each block's end."""
         self.image = image
+        self.image_part = part
         self._w.image = _dev_ptr(image, "image", torch.float64, self.grid.points)
+        self._w.image_part = _dev_ptr(part, "image_part", torch.float32, self.grid.points)
+        self._w.image_block = int(block)
 
     def set_source(self, src_dt2f: torch.Tensor | None, src=None):
         self.src_dt2f = src_dt2f

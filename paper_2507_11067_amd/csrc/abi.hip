@@ -147,6 +147,8 @@ static int wave_ok(const mms_wave *w) {
     if (w->radius < 1 || w->radius > 4) return MMS_EUNSUPPORTED;
     if (!grid_ok(&w->g, w->radius) || !w->c2 || !aligned16(w->c2)) return MMS_EINVAL;
     if (w->sponge_width < 0 || w->nt < 0) return MMS_EINVAL;
+    if (w->image_block < 0) return MMS_EINVAL;
+    if (w->image && w->image_block > 1 && !w->image_part) return MMS_EINVAL;
     if (w->src_dt2f && (w->src_z < 0 || w->src_z >= w->g.nz || w->src_y < 0 ||
                         w->src_y >= w->g.ny || w->src_x < 0 || w->src_x >= w->g.nx))
         return MMS_EINVAL;

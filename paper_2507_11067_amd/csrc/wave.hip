@@ -4,7 +4,8 @@
 // time level:
 //   u^{n+1} = G (2 u^n - G u^{n-1} + C2 S(u^n)) + dt^2 f^n delta_src
 // with the receiver reading d^n = u^n(z = 0) and the FP64 image
-// I += (u^{n+1})^2 fused in.  Adjoint step (exact transpose of the recurrence):
+// I += (u^{n+1})^2 fused in (every step, or per block of K steps summed in FP32,
+// which halves the image traffic).  Adjoint step (exact transpose of the recurrence):
 //   lam^n = 2 G lam^{n+1} - G^2 lam^{n+2} + S(C2 G lam^{n+1}) + R^T r^n
 //   grad += G lam^{n+1} S(u^n)                    (FP64)
 // S is the symmetric star, so S^T = S.  Both kernels stream z through an
@@ -36,6 +37,9 @@ struct WaveArgs {
     float *traces;        // FWD: [ny][nx] plane of level n, or NULL
     const float *resid;   // ADJ: [ny][nx] plane of level n, or NULL
     double *acc64;        // FWD: image, ADJ: grad (dense [nz][ny][nx]), or NULL
+    float *part;          // FWD: FP32 partial image of the current block, or NULL
+    int part_first;       // FWD with part: first step of a block (part = term)
+    int part_last;        // FWD with part: last step of a block (image += part + term)
     double *partials;     // ENERGY: one FP64 partial per block
     const float *src;     // device pointer to dt^2 f^n, or NULL
     int src_z, src_y, src_x;
@@ -294,7 +298,18 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                         for (int e = 0; e < 4; ++e) {
                             if (x0 + e < g.nx) {
                                 if constexpr (MODE == MODE_FWD) {
-                                    pa[e] += (double)r[e] * (double)r[e];
+                                    if (!a.part) {
+                                        pa[e] += (double)r[e] * (double)r[e];
+                                    } else {
+                                        // FP32 partial over the block, added in FP64 at its end
+                                        float *pp = a.part + dense + e;
+                                        const float t = r[e] * r[e];
+                                        const float sum = a.part_first ? t : *pp + t;
+                                        if (a.part_last)
+                                            pa[e] += (double)sum;
+                                        else
+                                            *pp = sum;
+                                    }
                                 } else if constexpr (GRAD) {
                                     pa[e] += (double)(a.c2s * gz * gown[e] * p1v[e] * o[NF - 1][e]);
                                 }
@@ -445,6 +460,12 @@ int wave_step(const mms_wave *w, int n, const float *up, const float *uc, float 
     a.out = un + o;
     a.traces = w->traces ? w->traces + (int64_t)n * w->g.ny * w->g.nx : nullptr;
     a.acc64 = w->image;
+    if (w->image && w->image_block > 1) {
+        const int K = w->image_block, ph = (n - 1) % K;
+        a.part = w->image_part;
+        a.part_first = ph == 0;
+        a.part_last = ph == K - 1 || n == w->nt - 1;
+    }
     a.src = (w->src_dt2f && n >= 0 && n < w->nt) ? w->src_dt2f + n : nullptr;
     a.src_z = (int)w->src_z;
     a.src_y = (int)w->src_y;

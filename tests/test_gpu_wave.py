@@ -168,6 +168,33 @@ def test_forward_run_vs_oracle(mms):
     assert rmax <= 1e-3 and ri <= 1e-3
 
 
+def test_blocked_image_matches_per_step(mms):
+    """Image summed per block of K = 8 steps in FP32 and added in FP64 (299 steps: the last
+    block has 3) against the FP64-per-step image and the oracle."""
+    n, nt = 40, 300
+    s = synth.wave_setup(n, nt, seed=22, sponge_width=8)
+    grid = mms.Grid(n, n, n)
+    imgs = []
+    for block in (1, 8):
+        image = torch.zeros((n, n, n), dtype=torch.float64, device=DEV)
+        part = torch.full((n, n, n), 7.0, device=DEV)      # stale contents are overwritten
+        w = mms.Wave(grid, T(s.c2), LAP, nt, 1.0, s.sponge_width, s.sponge_alpha,
+                     s.sponge_faces, s.src, T(s.src_dt2f))
+        w.set_image(image, part if block > 1 else None, block)
+        bufs = [grid.zeros(DEV) for _ in range(3)]
+        w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+        torch.cuda.synchronize()
+        imgs.append(image.cpu().numpy())
+    ow = oracle.Wave.from_setup(s, LAP)
+    z = ow.zeros()
+    ref = interior(ow.forward(z, z, image=True)["image"], grid)
+    r1, _ = rel_errors(imgs[0], ref)
+    r8, _ = rel_errors(imgs[1], ref)
+    d, _ = rel_errors(imgs[1], imgs[0])
+    print(f"image per step {r1:.2e}, per block of 8 {r8:.2e}, blocked vs per step {d:.2e}")
+    assert r1 <= 1e-5 and r8 <= 1e-5 and d <= 1e-6
+
+
 def test_energy_conserved_on_gpu(mms):
     n, nt = 40, 400
     grid, c2, f, src, _ = setup_small(mms, n, nt, 14)
