@@ -109,21 +109,22 @@ typedef struct mms_wave {
     const float *src_dt2f;/* device [nt]: dt^2 f(n dt), or NULL for no source       */
     float *traces;        /* device [nt][ny][nx]: d^n = u^n(z = 0), or NULL          */
     double *image;        /* device [nz][ny][nx] FP64: += (u^{n+1})^2, or NULL       */
-    float *image_part;    /* device [nz][ny][nx] FP32 workspace for image_block > 1  */
-    int32_t image_block;  /* K: 0 or 1 adds every step's term to image in FP64; K > 1 */
-                          /* sums the terms of K consecutive steps (n = 1+jK .. (j+1)K)*/
-                          /* in FP32 in image_part and adds that sum to image at the   */
-                          /* block's last step and at step nt-1                        */
+    float *acc_part;      /* device [nz][ny][nx] FP32 workspace for acc_block > 1    */
+    int32_t acc_block;    /* K for the FP64 accumulations (the image in forward steps, */
+                          /* the gradient in adjoint steps): 0 or 1 adds every step's  */
+                          /* term in FP64; K > 1 sums the terms of each block of K     */
+                          /* consecutive steps in FP32 in acc_part and adds that sum   */
+                          /* in FP64 at the block's last step                          */
     int32_t pad_;         /* unused, keep 0                                          */
 } mms_wave;
 
 /*
  * mms_wave_step -- one forward step n (1 <= n < nt): u_next = u^{n+1} from
  * u_prev = u^{n-1}, u_cur = u^n; records traces[n] = u^n(z = 0) and adds
- * (u^{n+1})^2 to image when those are set.  With image_block = K > 1 the image holds
- * every term of steps 1..n once n is a multiple of K or n = nt-1 (each block of K
- * steps is summed in FP32, relative error <= K 2^-24, and added in FP64); the steps of
- * a block must run in order.  u_next may equal u_prev (the update
+ * (u^{n+1})^2 to image when those are set.  With acc_block = K > 1 the image holds
+ * every term of steps 1..n once n is a multiple of K or n = nt-1 (forward blocks are
+ * steps 1+jK .. (j+1)K; each is summed in FP32, relative error <= K 2^-24, and added
+ * in FP64); the steps of a block must run in order.  u_next may equal u_prev (the update
  * reads and writes each cell in place); u_next must not overlap u_cur.
  */
 int mms_wave_step(const mms_wave *w, int n, const float *u_prev, const float *u_cur,
@@ -155,7 +156,10 @@ int mms_wave_forward(const mms_wave *w, int n_begin, int n_end, float *const *st
  * R^T adds resid[n] ([ny][nx], device, may be NULL) to the plane z = 0.  u_n is
  * needed when grad is set and n >= 1.  lam_n may equal lam_np2.
  * grad is dJ/d(c2 field): dJ/dC2 for c2_scale = 1, dJ/d(v^2) for c2_scale =
- * dt^2 / h^2.
+ * dt^2 / h^2.  With acc_block = K > 1 the gradient terms of each block of K steps,
+ * counted down from n = nt-1 (n = nt-1-jK .. nt-K-jK), are summed in FP32 in acc_part
+ * and added to grad in FP64 at the block's last step and at n = 1; the steps of a
+ * block must run in order.
  */
 int mms_wave_adjoint_step(const mms_wave *w, int n, const float *lam_np2, const float *lam_np1,
                           float *lam_n, const float *resid, const float *u_n, double *grad,

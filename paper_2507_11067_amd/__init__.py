@@ -148,10 +148,15 @@ class Wave:
         """FP64 image; with block K > 1 the terms of K consecutive steps are summed in the
         FP32 workspace `part` ([nz, ny, nx]) and added to the image at each block's end."""
         self.image = image
-        self.image_part = part
         self._w.image = _dev_ptr(image, "image", torch.float64, self.grid.points)
-        self._w.image_part = _dev_ptr(part, "image_part", torch.float32, self.grid.points)
-        self._w.image_block = int(block)
+        self.set_accumulation(part, block)
+
+    def set_accumulation(self, part: torch.Tensor | None, block: int):
+        """Block size K of the FP64 accumulations (image in forward steps, gradient in
+        adjoint steps) and their FP32 workspace ([nz, ny, nx]; needed when K > 1)."""
+        self.acc_part = part
+        self._w.acc_part = _dev_ptr(part, "acc_part", torch.float32, self.grid.points)
+        self._w.acc_block = int(block)
 
     def set_source(self, src_dt2f: torch.Tensor | None, src=None):
         self.src_dt2f = src_dt2f

@@ -29,8 +29,8 @@ class MmsWave(ctypes.Structure):
                 ("sponge_faces", ctypes.c_int32), ("nt", ctypes.c_int32),
                 ("src_z", ctypes.c_int64), ("src_y", ctypes.c_int64), ("src_x", ctypes.c_int64),
                 ("src_dt2f", ctypes.c_void_p), ("traces", ctypes.c_void_p),
-                ("image", ctypes.c_void_p), ("image_part", ctypes.c_void_p),
-                ("image_block", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("image", ctypes.c_void_p), ("acc_part", ctypes.c_void_p),
+                ("acc_block", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
 class MmsTti(ctypes.Structure):

@@ -39,6 +39,7 @@ class Problem:
     sponge_alpha: float = 0.0
     sponge_faces: int = 0
     checkpoint_every: int = 50
+    grad_block: int = 8        # adjoint steps whose gradient terms are summed in FP32
     stats: dict = field(default_factory=dict)
 
     @property
@@ -89,6 +90,9 @@ class WavePropagate(torch.autograd.Function):
         lam = [g.zeros(dev) for _ in range(3)]   # lam^n lives in lam[n % 3]
         seg = [g.zeros(dev) for _ in range(min(K, max(nt, 1)))]
         grad = torch.zeros((g.nz, g.ny, g.nx), dtype=torch.float64, device=dev)
+        if prob.grad_block > 1:
+            # each block of grad_block adjoint steps is summed in FP32, then added in FP64
+            wa.set_accumulation(torch.empty((g.nz, g.ny, g.nx), device=dev), prob.grad_block)
         recomputed = 0
         w_src = prob.wave(m)               # recompute: same source, no receivers
         for si in range(len(ctx.ckpts) - 1, -1, -1):

@@ -147,8 +147,8 @@ static int wave_ok(const mms_wave *w) {
     if (w->radius < 1 || w->radius > 4) return MMS_EUNSUPPORTED;
     if (!grid_ok(&w->g, w->radius) || !w->c2 || !aligned16(w->c2)) return MMS_EINVAL;
     if (w->sponge_width < 0 || w->nt < 0) return MMS_EINVAL;
-    if (w->image_block < 0) return MMS_EINVAL;
-    if (w->image && w->image_block > 1 && !w->image_part) return MMS_EINVAL;
+    if (w->acc_block < 0) return MMS_EINVAL;
+    if (w->image && w->acc_block > 1 && !w->acc_part) return MMS_EINVAL;
     if (w->src_dt2f && (w->src_z < 0 || w->src_z >= w->g.nz || w->src_y < 0 ||
                         w->src_y >= w->g.ny || w->src_x < 0 || w->src_x >= w->g.nx))
         return MMS_EINVAL;
@@ -256,6 +256,7 @@ int mms_wave_adjoint_step(const mms_wave *w, int n, const float *lam_np2, const 
     if (n < 0 || n >= w->nt || !lam_np2 || !lam_n) return MMS_EINVAL;
     if (n >= 1 && !lam_np1) return MMS_EINVAL;
     if (n >= 1 && grad && !u_n) return MMS_EINVAL;
+    if (n >= 1 && grad && w->acc_block > 1 && !w->acc_part) return MMS_EINVAL;
     const int64_t bytes = grid_elems(&w->g) * (int64_t)sizeof(float);
     if (lam_np1 && overlap(lam_np1, bytes, lam_n, bytes)) return MMS_EINVAL;
     if (lam_np2 != lam_n && overlap(lam_np2, bytes, lam_n, bytes)) return MMS_EINVAL;

@@ -37,9 +37,9 @@ struct WaveArgs {
     float *traces;        // FWD: [ny][nx] plane of level n, or NULL
     const float *resid;   // ADJ: [ny][nx] plane of level n, or NULL
     double *acc64;        // FWD: image, ADJ: grad (dense [nz][ny][nx]), or NULL
-    float *part;          // FWD: FP32 partial image of the current block, or NULL
-    int part_first;       // FWD with part: first step of a block (part = term)
-    int part_last;        // FWD with part: last step of a block (image += part + term)
+    float *part;          // FP32 partial of the current block (image or grad), or NULL
+    int part_first;       // with part: first step of a block (part = term)
+    int part_last;        // with part: last step of a block (acc64 += part + term)
     double *partials;     // ENERGY: one FP64 partial per block
     const float *src;     // device pointer to dt^2 f^n, or NULL
     int src_z, src_y, src_x;
@@ -311,7 +311,17 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                                             *pp = sum;
                                     }
                                 } else if constexpr (GRAD) {
-                                    pa[e] += (double)(a.c2s * gz * gown[e] * p1v[e] * o[NF - 1][e]);
+                                    const float t = a.c2s * gz * gown[e] * p1v[e] * o[NF - 1][e];
+                                    if (!a.part) {
+                                        pa[e] += (double)t;
+                                    } else {
+                                        float *pp = a.part + dense + e;
+                                        const float sum = a.part_first ? t : *pp + t;
+                                        if (a.part_last)
+                                            pa[e] += (double)sum;
+                                        else
+                                            *pp = sum;
+                                    }
                                 }
                             }
                         }
@@ -460,9 +470,9 @@ int wave_step(const mms_wave *w, int n, const float *up, const float *uc, float 
     a.out = un + o;
     a.traces = w->traces ? w->traces + (int64_t)n * w->g.ny * w->g.nx : nullptr;
     a.acc64 = w->image;
-    if (w->image && w->image_block > 1) {
-        const int K = w->image_block, ph = (n - 1) % K;
-        a.part = w->image_part;
+    if (w->image && w->acc_block > 1) {
+        const int K = w->acc_block, ph = (n - 1) % K;
+        a.part = w->acc_part;
         a.part_first = ph == 0;
         a.part_last = ph == K - 1 || n == w->nt - 1;
     }
@@ -491,6 +501,13 @@ int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1
     if (grad) {
         a.fu = un + o;
         a.acc64 = grad;
+        if (w->acc_block > 1) {
+            // blocks counted down from n = nt-1, the order the adjoint runs in
+            const int K = w->acc_block, ph = (w->nt - 1 - n) % K;
+            a.part = w->acc_part;
+            a.part_first = ph == 0;
+            a.part_last = ph == K - 1 || n == 1;
+        }
         return launch_mode<MODE_ADJ, true>(a, &w->g, w->radius, s);
     }
     return launch_mode<MODE_ADJ, false>(a, &w->g, w->radius, s);

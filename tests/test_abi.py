@@ -94,11 +94,11 @@ def test_wave_validation(L):
     vp = ctypes.c_void_p
     a, b, c = vp(0x100000), vp(0x800000), vp(0x1000000)
     assert L.mms_wave_step(ctypes.byref(w), 0, a, b, c, None) == -1      # n out of range
-    w.image, w.image_block = vp(0x3000000), 8                            # block without workspace
+    w.image, w.acc_block = vp(0x3000000), 8                            # block without workspace
     assert L.mms_wave_step(ctypes.byref(w), 1, a, b, c, None) == -1
-    w.image_block = -1
+    w.acc_block = -1
     assert L.mms_wave_step(ctypes.byref(w), 1, a, b, c, None) == -1
-    w.image, w.image_block = None, 0
+    w.image, w.acc_block = None, 0
     assert L.mms_wave_step(ctypes.byref(w), 10, a, b, c, None) == -1
     assert L.mms_wave_step(ctypes.byref(w), 1, a, b, b, None) == -1      # u_next aliases u_cur
     assert L.mms_wave_step(ctypes.byref(w), 1, None, b, c, None) == -1

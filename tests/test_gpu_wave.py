@@ -264,6 +264,26 @@ def test_checkpointing_gives_identical_gradient(mms):
     assert torch.count_nonzero(grads[0][0]) > 0
 
 
+def test_blocked_gradient_matches_per_step(mms):
+    """Gradient terms summed per block of 8 adjoint steps in FP32 (119 steps: the last block,
+    ending at n = 1, has 7) against every term added in FP64."""
+    from paper_2507_11067_amd.autograd import misfit, propagate
+    n, nt = 32, 120
+    s, grid, m, prob = autograd_problem(mms, n, nt, 42, K=50)
+    d_obs = torch.zeros((nt, n, n), device=DEV)
+    grads = []
+    for block in (1, 8, 5):
+        prob.grad_block = block
+        mt = T(m).requires_grad_(True)
+        J = misfit(propagate(mt, grid.zeros(DEV), grid.zeros(DEV), prob), d_obs)
+        J.backward()
+        grads.append(mt.grad.clone().cpu().numpy())
+    for gb in grads[1:]:
+        d, _ = rel_errors(interior(gb, grid), interior(grads[0], grid))
+        print(f"blocked vs per-step gradient: {d:.2e}")
+        assert d <= 1e-6
+
+
 def test_gradient_vs_oracle_64(mms):
     """CPU reference gradient: the workload recipe at 64^3 (W = 8, 1000 steps, checkpoints
     every 50), gradient of the receiver misfit w.r.t. v^2 against the FP64 oracle."""
