@@ -15,8 +15,16 @@
 //    complete after each plane and the window shifts by one;
 //  * a lane reads 12 consecutive cells of one input row (three 16-byte LDS
 //    words) and applies all (2r+1) x (2r+1) weights of that dy to them, so LDS
-//    traffic is 3 words per (2r+1)^2 * 4 FMAs; the weights are uniform and come
-//    from the kernel-argument segment through the scalar unit.
+//    traffic is 3 words per (2r+1)^2 * 4 FMAs.
+// Where the weights come from sets the FMA rate on gfx950: an FMA that reads
+// one operand from a scalar register issues at about 75 TFLOP/s chip-wide,
+// one with all operands in vector registers at about 110.  At radius 2 and 4
+// the weights are therefore copied once into LDS, laid out [dy][dz][dx] with
+// rows padded to 12 floats, and every lane reads the 2r+1 weights of one
+// (dy, dz) row as broadcast LDS loads into vector registers; each is used by
+// 4 FMAs.  At radius 1 and 3 this costs more in LDS
+// issue than it gains (measured), and the weights stay in scalar registers,
+// loaded from the kernel-argument segment.
 #include <type_traits>
 
 #include "mms_internal.h"
@@ -29,7 +37,7 @@ struct BoxArgs {
     float c[729];  // [dz][dy][dx] for radius r, (2r+1)^3 used
 };
 
-template <int R, int TX, int TY>
+template <int R, int TX, int TY, bool LDSW>
 __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
     constexpr int W = 2 * R + 1;
     constexpr int BX = 4 * TX;
@@ -39,7 +47,9 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
     constexpr int NT = TX * TY;
     constexpr int NL = LW4 * LH;              // float4 per plane tile
     constexpr int NLK = (NL + NT - 1) / NT;
+    constexpr int CP = 12;                    // padded weights per (dy, dz) row in LDS
     __shared__ float4 tile[2][LH][LW4];
+    __shared__ __attribute__((aligned(16))) float wl[LDSW ? W : 1][LDSW ? W : 1][CP];
 
     const Geom &g = a.g;
     int b = mms_xcd_remap(blockIdx.x, gridDim.x);
@@ -57,6 +67,10 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
     const int ylim = g.ny + g.H;
     const int64_t sy = g.sy, sz = g.sz;
 
+    if (LDSW) {
+        // [dz][dy][dx] -> [dy][dz][dx]; the first barrier below publishes it
+        for (int i = tid; i < W * W * W; i += NT) wl[(i / W) % W][i / (W * W)][i % W] = a.c[i];
+    }
     // cooperative tile load: item i -> (row, col4) of the tile
     int64_t l_off[NLK];
     bool l_ok[NLK];
@@ -115,7 +129,7 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
                         const int zo = zi - dz;  // output plane fed through c[dz]
                         if (zo < zb || zo >= ze) continue;
                     }
-                    const float *cc = cdy + (dz + R) * W * W;
+                    const float *cc = LDSW ? &wl[dy + R][dz + R][0] : cdy + (dz + R) * W * W;
 #pragma unroll
                     for (int dx = -R; dx <= R; ++dx) {
                         const float ck = cc[dx + R];
@@ -186,7 +200,9 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     for (int i = 0; i < W * W * W; ++i) a.c[i] = coeffs[i];
     const int64_t nblk = (int64_t)g.ntx * g.nty * g.nzc;
     if (nblk > 0x7fffffff) return MMS_EINVAL;
-    hipLaunchKernelGGL((box_valu_kernel<R, TX, TY>), dim3((unsigned)nblk), dim3(TX * TY), 0, s, a);
+    constexpr bool LDSW = R == 2 || R == 4;
+    hipLaunchKernelGGL((box_valu_kernel<R, TX, TY, LDSW>), dim3((unsigned)nblk), dim3(TX * TY), 0, s,
+                       a);
     return check_launch("box_valu_kernel");
 }
 
