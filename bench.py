@@ -875,6 +875,9 @@ def collect_counters(args):
         lines.append(f"  {name:12s} {vals}  src {e['source']} {e['source_sha']}")
         lines.append(f"      command: {e['command']}")
     open(os.path.join(PROFILES, "counters_512.txt"), "w").write("\n".join(lines) + "\n")
+    # copies beside the raw rocprofv3 output, for runs whose tree is not kept
+    json.dump(summary, open(os.path.join(out_root, "counters_512.json"), "w"), indent=1)
+    open(os.path.join(out_root, "counters_512.txt"), "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 

@@ -13,7 +13,10 @@
 // and reads its 12-cell row windows as three 16-byte LDS words per row.  No
 // plane depends on another, so z chunks need no halo planes.  Outputs are
 // written with streaming stores; block indices are remapped per XCD as in the
-// 3-D sweeps.
+// 3-D sweeps.  The radius-3 box reads its 49 weights from LDS into vector
+// registers once (an FMA with a scalar-register operand issues at a lower rate
+// on gfx950); at the other radii that costs more occupancy than it gains
+// (measured).
 #include "mms_internal.h"
 
 namespace mms {
@@ -37,7 +40,9 @@ __global__ void __launch_bounds__(TX *TY) plane_kernel(PlaneArgs a) {
     constexpr int NH = 2 * R * LW4 + 2 * BY;  // halo words per plane
     constexpr int NHK = (NH + NT - 1) / NT;
     constexpr int NWIN = NY + 2 * R;          // LDS rows one lane reads
+    constexpr bool LDSW = SHAPE == SH_BOX2D && R == 3;
     __shared__ float4 tile[2][LH][LW4];
+    __shared__ float wl[LDSW ? W * W : 1];
 
     const Geom &g = a.g;
     int b = mms_xcd_remap(blockIdx.x, gridDim.x);
@@ -100,6 +105,10 @@ __global__ void __launch_bounds__(TX *TY) plane_kernel(PlaneArgs a) {
             if (tid + k * NT < NH) t[h_lds[k]] = halo[k];
     };
 
+    if (LDSW) {
+        // published by the first barrier below
+        for (int i = tid; i < W * W; i += NT) wl[i] = a.c[i];
+    }
     float4 own[NY], hreg[NHK];
     load_plane(zb, own, hreg);
     tile_store(0, own, hreg);
@@ -163,7 +172,7 @@ __global__ void __launch_bounds__(TX *TY) plane_kernel(PlaneArgs a) {
                     if (dy < -R || dy > R) continue;
 #pragma unroll
                     for (int dx = -R; dx <= R; ++dx) {
-                        const float cc = c[(dy + R) * W + dx + R];
+                        const float cc = LDSW ? wl[(dy + R) * W + dx + R] : c[(dy + R) * W + dx + R];
 #pragma unroll
                         for (int e = 0; e < 4; ++e) o[j][e] = fmaf(cc, w[4 + e + dx], o[j][e]);
                     }
