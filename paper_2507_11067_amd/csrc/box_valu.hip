@@ -18,13 +18,12 @@
 //    traffic is 3 words per (2r+1)^2 * 4 FMAs.
 // Where the weights come from sets the FMA rate on gfx950: an FMA that reads
 // one operand from a scalar register issues at about 75 TFLOP/s chip-wide,
-// one with all operands in vector registers at about 110.  At radius 2 and 4
+// one with all operands in vector registers at about 110.  From radius 2 on
 // the weights are therefore copied once into LDS, laid out [dy][dz][dx] with
 // rows padded to 12 floats, and every lane reads the 2r+1 weights of one
 // (dy, dz) row as broadcast LDS loads into vector registers; each is used by
-// 4 FMAs.  At radius 1 and 3 this costs more in LDS
-// issue than it gains (measured), and the weights stay in scalar registers,
-// loaded from the kernel-argument segment.
+// 4 FMAs.  At radius 1 the sweep is bound by HBM, and the weights stay in
+// scalar registers, loaded from the kernel-argument segment.
 #include <type_traits>
 
 #include "mms_internal.h"
@@ -200,7 +199,7 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     for (int i = 0; i < W * W * W; ++i) a.c[i] = coeffs[i];
     const int64_t nblk = (int64_t)g.ntx * g.nty * g.nzc;
     if (nblk > 0x7fffffff) return MMS_EINVAL;
-    constexpr bool LDSW = R == 2 || R == 4;
+    constexpr bool LDSW = R >= 2;
     hipLaunchKernelGGL((box_valu_kernel<R, TX, TY, LDSW>), dim3((unsigned)nblk), dim3(TX * TY), 0, s,
                        a);
     return check_launch("box_valu_kernel");

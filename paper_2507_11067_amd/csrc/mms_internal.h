@@ -28,7 +28,22 @@ struct Geom {
     int64_t sy, sz;
     int ntx, nty, nzc;  // tile counts along x, y and z chunks
     int zchunk;
+    int txa;            // kernels with balanced x tiles: active lanes per tile row
 };
+
+// Balanced x tiles: the fewest tiles of at most `lanes` 16-byte words that cover
+// a row of nx cells, all of one width (in words).  Blocks of a one-block-per-CU
+// launch then move the same bytes, where fixed-width tiles would leave the last
+// tile of a row partly empty (at nx = 400 and 64 lanes: 200 + 200 cells instead
+// of 256 + 144).
+inline int balanced_tile_words(int nx, int lanes, int *ntx) {
+    const int words = (nx + 3) / 4;
+    int n = (words + lanes - 1) / lanes;
+    if (n < 1) n = 1;
+    *ntx = n;
+    const int w = (words + n - 1) / n;
+    return w < 1 ? 1 : w;
+}
 
 int zchunk_override(int shape, int precision);
 

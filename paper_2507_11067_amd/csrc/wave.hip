@@ -52,7 +52,7 @@ template <int R, int MODE, bool GRAD, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     constexpr int NF = (MODE == MODE_ADJ && GRAD) ? 2 : 1;  // stencil fields
     constexpr int Q = 2 * R + 1;
-    constexpr int BX = 4 * TX, BY = TY;
+    constexpr int BY = TY;
     constexpr int LW4 = TX + 2, LH = BY + 2 * R;
     constexpr int NT = TX * TY;
     constexpr int NH = 2 * R * LW4 + 2 * BY;
@@ -69,7 +69,11 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     const int zci = b / g.nty;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int xt = txi * BX, yt = tyi * BY;
+    // balanced x tiles: txa <= TX lanes of each row own words, the rest only help
+    // with the halo and the barriers
+    const int txa = g.txa, lw = txa + 2, bxa = 4 * txa;
+    const bool lane_on = tx < txa;
+    const int xt = txi * bxa, yt = tyi * BY;
     const int x0 = xt + 4 * tx, y = yt + ty;
     const int zb = zci * g.zchunk;
     const int ze = min(zb + g.zchunk, g.nz);
@@ -79,7 +83,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     const int W = a.sponge_w;
     const float sa = a.sponge_a;
 
-    const bool own_ok = (x0 <= nx4) && (y < ylim);
+    const bool own_ok = lane_on && (x0 <= nx4) && (y < ylim);
     const int64_t own_off = (int64_t)y * sy + x0;
     // sponge factors gy(y) gx(x) of the lane's own cells
     float gown[4];
@@ -90,26 +94,27 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     }
     int64_t h_off[NHK];
     int h_lds[NHK];
-    bool h_ok[NHK];
+    bool h_ok[NHK], h_on[NHK];  // h_on: item k is one of this tile's halo words
     float hg[NHK][4];  // ADJ: gy gx of the halo cells (C2 G lam is formed on load)
 #pragma unroll
     for (int k = 0; k < NHK; ++k) {
         const int i = tid + k * NT;
         int row, lrow, col4, x;
-        if (i < 2 * R * LW4) {
-            const int hr = i / LW4, hc = i % LW4;
+        if (i < 2 * R * lw) {
+            const int hr = i / lw, hc = i % lw;
             row = hr < R ? yt - R + hr : yt + BY + (hr - R);
             lrow = hr < R ? hr : hr + BY;
             col4 = hc;
             x = xt - 4 + 4 * hc;
         } else {
-            const int j = i - 2 * R * LW4;
+            const int j = i - 2 * R * lw;
             row = yt + j / 2;
             lrow = R + j / 2;
-            col4 = (j & 1) ? LW4 - 1 : 0;
-            x = (j & 1) ? xt + BX : xt - 4;
+            col4 = (j & 1) ? txa + 1 : 0;
+            x = (j & 1) ? xt + bxa : xt - 4;
         }
-        h_ok[k] = (i < NH) && (row < ylim) && (x <= nx4);
+        h_on[k] = i < 2 * R * lw + 2 * BY;
+        h_ok[k] = h_on[k] && (row < ylim) && (x <= nx4);
         h_off[k] = (int64_t)row * sy + x;
         h_lds[k] = lrow * LW4 + col4;
         if constexpr (MODE == MODE_ADJ) {
@@ -153,10 +158,10 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             float4 *t = &ring[f][slot][0][0];
-            t[(R + ty) * LW4 + tx + 1] = own[f];
+            if (lane_on) t[(R + ty) * LW4 + tx + 1] = own[f];
 #pragma unroll
             for (int k = 0; k < NHK; ++k)
-                if (tid + k * NT < NH) t[h_lds[k]] = halo[f][k];
+                if (h_on[k]) t[h_lds[k]] = halo[f][k];
         }
     };
 
@@ -234,7 +239,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                     for (int e = 0; e < 4; ++e) o[f][e] = s[e];
                 }
                 const float gz = gaxis(z, g.nz, W, sa, zlo, zhi);
-                const bool live = y < g.ny && x0 < g.nx;
+                const bool live = lane_on && y < g.ny && x0 < g.nx;
                 const int64_t dense = ((int64_t)z * g.ny + y) * g.nx + x0;
                 float *po = a.out ? a.out + (int64_t)z * sz + own_off : nullptr;
                 const float p0v[4] = {pw0.x, pw0.y, pw0.z, pw0.w};
@@ -418,7 +423,7 @@ void fill_geom(Geom &g, const mms_grid *gd) {
     g.nz = (int)gd->nz;
     g.sy = gd->sy;
     g.sz = gd->sz;
-    g.ntx = (g.nx + 4 * TX - 1) / (4 * TX);
+    g.txa = balanced_tile_words(g.nx, TX, &g.ntx);
     g.nty = (g.ny + TY - 1) / TY;
     // one block per CU (LDS-bound).  The two-field adjoint fills two rings per
     // block, so its chunk count follows the round model; the one-field kernels
