@@ -154,7 +154,7 @@ constexpr int NOWN = 9;    // Dzz p, Dzz q, p^{n-1}, q^{n-1}, C2, eps, delta, th
 
 template <int R, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
-    constexpr int BX = 4 * TX, BY = TY;
+    constexpr int BY = TY;
     constexpr int LW4 = TX + 2, LH = BY + 2 * R;
     constexpr int NT = TX * TY;
     constexpr int NH = 2 * R * LW4 + 2 * BY;
@@ -169,7 +169,11 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
     const int zci = b / g.nty;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int xt = txi * BX, yt = tyi * BY;
+    // balanced x tiles: txa <= TX lanes of each row own words, the rest only help
+    // with the halo and the barriers
+    const int txa = g.txa, lw = txa + 2, bxa = 4 * txa;
+    const bool lane_on = tx < txa;
+    const int xt = txi * bxa, yt = tyi * BY;
     const int x0 = xt + 4 * tx, y = yt + ty;
     const int zb = zci * g.zchunk;
     const int ze = min(zb + g.zchunk, g.nz);
@@ -179,7 +183,7 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
     const int W = a.sponge_w;
     const float sa = a.sponge_a;
 
-    const bool own_ok = (x0 <= nx4) && (y < ylim);
+    const bool own_ok = lane_on && (x0 <= nx4) && (y < ylim);
     const int64_t own_off = (int64_t)y * sy + x0;
     float gown[4];
     {
@@ -189,25 +193,26 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
     }
     int64_t h_off[NHK];
     int h_lds[NHK];
-    bool h_ok[NHK];
+    bool h_ok[NHK], h_on[NHK];  // h_on: item k is one of this tile's halo words
 #pragma unroll
     for (int k = 0; k < NHK; ++k) {
         const int i = tid + k * NT;
         int row, lrow, col4, x;
-        if (i < 2 * R * LW4) {
-            const int hr = i / LW4, hc = i % LW4;
+        if (i < 2 * R * lw) {
+            const int hr = i / lw, hc = i % lw;
             row = hr < R ? yt - R + hr : yt + BY + (hr - R);
             lrow = hr < R ? hr : hr + BY;
             col4 = hc;
             x = xt - 4 + 4 * hc;
         } else {
-            const int j = i - 2 * R * LW4;
+            const int j = i - 2 * R * lw;
             row = yt + j / 2;
             lrow = R + j / 2;
-            col4 = (j & 1) ? LW4 - 1 : 0;
-            x = (j & 1) ? xt + BX : xt - 4;
+            col4 = (j & 1) ? txa + 1 : 0;
+            x = (j & 1) ? xt + bxa : xt - 4;
         }
-        h_ok[k] = (i < NH) && (row < ylim) && (x <= nx4);
+        h_on[k] = i < 2 * R * lw + 2 * BY;
+        h_ok[k] = h_on[k] && (row < ylim) && (x <= nx4);
         h_off[k] = (int64_t)row * sy + x;
         h_lds[k] = lrow * LW4 + col4;
     }
@@ -228,10 +233,10 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
 #pragma unroll
         for (int f = 0; f < NTILE; ++f) {
             float4 *t = &tile[buf][f][0][0];
-            t[(R + ty) * LW4 + tx + 1] = tw[f][0];
+            if (lane_on) t[(R + ty) * LW4 + tx + 1] = tw[f][0];
 #pragma unroll
             for (int k = 0; k < NHK; ++k)
-                if (tid + k * NT < NH) t[h_lds[k]] = tw[f][1 + k];
+                if (h_on[k]) t[h_lds[k]] = tw[f][1 + k];
         }
     };
 
@@ -373,7 +378,7 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
                     rq[e] += srcv;
                 }
         }
-        if (y < g.ny && x0 < g.nx) {
+        if (lane_on && y < g.ny && x0 < g.nx) {
             float *pp_ = a.pn + (int64_t)z * sz + own_off;
             float *qq_ = a.qn + (int64_t)z * sz + own_off;
             if (x0 + 3 < g.nx) {
@@ -445,7 +450,7 @@ int launch_tti(const mms_wave *w, const mms_tti *t, int n, const float *pp, cons
     g.nz = (int)gd->nz;
     g.sy = gd->sy;
     g.sz = gd->sz;
-    g.ntx = (g.nx + 4 * TTX - 1) / (4 * TTX);
+    g.txa = balanced_tile_words(g.nx, TTX, &g.ntx);
     g.nty = (g.ny + TTY - 1) / TTY;
     g.zchunk = pick_zchunk_rounds(g.nz, (int64_t)g.ntx * g.nty,
                                   launch_slots(reinterpret_cast<const void *>(&tti_kernel<R, TTX, TTY>),
