@@ -8,9 +8,11 @@
 // which halves the image traffic).  Adjoint step (exact transpose of the recurrence):
 //   lam^n = 2 G lam^{n+1} - G^2 lam^{n+2} + S(C2 G lam^{n+1}) + R^T r^n
 //   grad += G lam^{n+1} S(u^n)                    (FP64)
-// S is the symmetric star, so S^T = S.  Both kernels stream z through an
-// (x, y) tile like the star sweep: the stencil operands travel through a
-// register queue of 2r+1 planes (z terms) and a double-buffered LDS plane
+// S is the symmetric star, so S^T = S.  The gradient is a second pass of the same
+// kernel with u^n as its stencil field (one stencil field per pass keeps the tile
+// at 256 x 16 cells and four waves per SIMD).  Every pass streams z through an
+// (x, y) tile like the star sweep: the stencil operand travels through a
+// register queue of 2r+1 planes (z terms) and an LDS ring of r+2 plane tiles
 // (x and y terms); the point-wise operands are requested one plane ahead.
 // The intermediate fields S(u^n), C2 G lam^{n+1} and S(C2 G lam^{n+1}) never
 // reach memory (the paper's thread-private intermediate buffers, Sec. IV-G).
@@ -21,22 +23,22 @@
 namespace mms {
 namespace {
 
-enum { MODE_FWD = 0, MODE_ADJ = 1, MODE_ENERGY = 2 };
+enum { MODE_FWD = 0, MODE_ADJ = 1, MODE_ENERGY = 2, MODE_GRAD = 3 };
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 struct WaveArgs {
     Geom g;
     float c[9];           // per-axis weights, k + r (symmetric)
-    const float *f0;      // stencil field: u^n (FWD, ENERGY) or lam^{n+1} (ADJ)
-    const float *fu;      // ADJ: u^n (second stencil field, for the gradient)
+    const float *f0;      // stencil field: u^n (FWD, ENERGY, GRAD) or lam^{n+1} (ADJ)
     const float *c2;      // c2 field (interior origin); C2 = c2s * c2
     float c2s;
-    const float *p0;      // point-wise: u^{n-1} (FWD), lam^{n+2} (ADJ), u^{n+1} (ENERGY)
+    const float *p0;      // point-wise: u^{n-1} (FWD), lam^{n+2} (ADJ), u^{n+1} (ENERGY),
+                          // lam^{n+1} (GRAD)
     float *out;           // u^{n+1} (FWD), lam^n (ADJ)
     float *traces;        // FWD: [ny][nx] plane of level n, or NULL
     const float *resid;   // ADJ: [ny][nx] plane of level n, or NULL
-    double *acc64;        // FWD: image, ADJ: grad (dense [nz][ny][nx]), or NULL
+    double *acc64;        // FWD: image, GRAD: grad (dense [nz][ny][nx]), or NULL
     float *part;          // FP32 partial of the current block (image or grad), or NULL
     int part_first;       // with part: first step of a block (part = term)
     int part_last;        // with part: last step of a block (acc64 += part + term)
@@ -48,9 +50,8 @@ struct WaveArgs {
     int faces;
 };
 
-template <int R, int MODE, bool GRAD, int TX, int TY>
+template <int R, int MODE, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
-    constexpr int NF = (MODE == MODE_ADJ && GRAD) ? 2 : 1;  // stencil fields
     constexpr int Q = 2 * R + 1;
     constexpr int BY = TY;
     constexpr int LW4 = TX + 2, LH = BY + 2 * R;
@@ -58,7 +59,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     constexpr int NH = 2 * R * LW4 + 2 * BY;
     constexpr int NHK = (NH + NT - 1) / NT;
     constexpr int NR = R + 2;   // LDS ring: planes z .. z+R+1
-    __shared__ float4 ring[NF][NR][LH][LW4];
+    __shared__ float4 ring[NR][LH][LW4];
     __shared__ double sred[NT / 64];
 
     const Geom &g = a.g;
@@ -134,58 +135,53 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     auto mul4 = [](float4 v, const float *s, float t) {
         return make_float4(v.x * s[0] * t, v.y * s[1] * t, v.z * s[2] * t, v.w * s[3] * t);
     };
-    // stencil field f of plane z at the lane's own cells / halo item k
-    auto own_field = [&](int f, int z) -> float4 {
-        if (MODE == MODE_ADJ && f == 0) {
+    // stencil field of plane z at the lane's own cells / halo item k (ADJ: C2 G lam)
+    auto own_field = [&](int z) -> float4 {
+        if (MODE == MODE_ADJ) {
             const float4 l = ld(a.f0, z, own_off, own_ok);
             const float4 c = ld(a.c2, z, own_off, own_ok);
             const float gz = a.c2s * gaxis(z, g.nz, W, sa, zlo, zhi);
             return mul4(make_float4(l.x * c.x, l.y * c.y, l.z * c.z, l.w * c.w), gown, gz);
         }
-        return ld(f == 0 ? a.f0 : a.fu, z, own_off, own_ok);
+        return ld(a.f0, z, own_off, own_ok);
     };
-    auto halo_field = [&](int f, int z, int k) -> float4 {
-        if (MODE == MODE_ADJ && f == 0) {
+    auto halo_field = [&](int z, int k) -> float4 {
+        if (MODE == MODE_ADJ) {
             const float4 l = ld(a.f0, z, h_off[k], h_ok[k]);
             const float4 c = ld(a.c2, z, h_off[k], h_ok[k]);
             const float gz = a.c2s * gaxis(z, g.nz, W, sa, zlo, zhi);
             return mul4(make_float4(l.x * c.x, l.y * c.y, l.z * c.z, l.w * c.w), hg[k], gz);
         }
-        return ld(f == 0 ? a.f0 : a.fu, z, h_off[k], h_ok[k]);
+        return ld(a.f0, z, h_off[k], h_ok[k]);
     };
     // tile of one plane (own cells + halo) into ring slot `slot`
-    auto ring_store = [&](int slot, const float4 *own, float4 (*halo)[NHK]) {
+    auto ring_store = [&](int slot, const float4 &own, const float4 *halo) {
+        float4 *t = &ring[slot][0][0];
+        if (lane_on) t[(R + ty) * LW4 + tx + 1] = own;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            float4 *t = &ring[f][slot][0][0];
-            if (lane_on) t[(R + ty) * LW4 + tx + 1] = own[f];
-#pragma unroll
-            for (int k = 0; k < NHK; ++k)
-                if (h_on[k]) t[h_lds[k]] = halo[f][k];
-        }
+        for (int k = 0; k < NHK; ++k)
+            if (h_on[k]) t[h_lds[k]] = halo[k];
     };
 
-    float4 q[NF][Q];
-    float4 hreg[NF][NHK];
+    float4 q[Q];
+    float4 hreg[NHK];
     // prologue: planes zb-R .. zb+R into the queue; tiles of planes zb .. zb+R into the ring
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
-#pragma unroll
-        for (int i = 0; i < Q; ++i) q[f][i] = own_field(f, zb - R + i);
+    for (int i = 0; i < Q; ++i) q[i] = own_field(zb - R + i);
 #pragma unroll
     for (int i = 0; i <= R; ++i) {
-        float4 own[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            own[f] = q[f][R + i];
-#pragma unroll
-            for (int k = 0; k < NHK; ++k) hreg[f][k] = halo_field(f, zb + i, k);
-        }
-        ring_store((zb + i) % NR, own, hreg);
+        for (int k = 0; k < NHK; ++k) hreg[k] = halo_field(zb + i, k);
+        ring_store((zb + i) % NR, q[R + i], hreg);
     }
     // point-wise operands of the first plane
+    // second point-wise operand: lam^{n+1} (ADJ), C2 (FWD, ENERGY), none (GRAD)
+    auto ld_pw1 = [&](int z) -> float4 {
+        if constexpr (MODE == MODE_GRAD) return zero4;
+        return ld(MODE == MODE_ADJ ? a.f0 : a.c2, z, own_off, own_ok);
+    };
     float4 pw0 = ld(a.p0, zb, own_off, own_ok);
-    float4 pw1 = (MODE == MODE_ADJ) ? ld(a.f0, zb, own_off, own_ok) : ld(a.c2, zb, own_off, own_ok);
+    float4 pw1 = ld_pw1(zb);
     __syncthreads();
 
     const float *c = a.c;
@@ -196,37 +192,32 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
         for (int ph = 0; ph < Q; ++ph) {
             if (z < ze) {
                 const bool more = z + 1 < ze;
-                float4 nq[NF];
+                float4 nq = zero4;
                 float4 npw0 = zero4, npw1 = zero4;
                 if (more) {
                     // the tile of plane z+R+1 is requested together with the neighbouring
                     // tiles that read the same rows, and parked in the ring
+                    nq = own_field(z + R + 1);
 #pragma unroll
-                    for (int f = 0; f < NF; ++f) {
-                        nq[f] = own_field(f, z + R + 1);
-#pragma unroll
-                        for (int k = 0; k < NHK; ++k) hreg[f][k] = halo_field(f, z + R + 1, k);
-                    }
+                    for (int k = 0; k < NHK; ++k) hreg[k] = halo_field(z + R + 1, k);
                     npw0 = ld(a.p0, z + 1, own_off, own_ok);
-                    npw1 = (MODE == MODE_ADJ) ? ld(a.f0, z + 1, own_off, own_ok)
-                                              : ld(a.c2, z + 1, own_off, own_ok);
+                    npw1 = ld_pw1(z + 1);
                 }
-                float o[NF][4];
+                // o = S f at the lane's 4 cells
+                float o[4] = {0.f, 0.f, 0.f, 0.f};
+                const float4 *t = &ring[z % NR][0][0];
+                const float4 ctr = q[(ph + R) % Q];
 #pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const float4 *t = &ring[f][z % NR][0][0];
-                    const float4 ctr = q[f][(ph + R) % Q];
-                    float s[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int k = -R; k <= R; ++k) {
-                        const float4 vz = q[f][(ph + R + k + Q) % Q];
-                        const float4 vy = k == 0 ? ctr : t[(R + ty + k) * LW4 + tx + 1];
-                        const float ck = c[R + k];
-                        s[0] = fmaf(ck, vz.x + vy.x, s[0]);
-                        s[1] = fmaf(ck, vz.y + vy.y, s[1]);
-                        s[2] = fmaf(ck, vz.z + vy.z, s[2]);
-                        s[3] = fmaf(ck, vz.w + vy.w, s[3]);
-                    }
+                for (int k = -R; k <= R; ++k) {
+                    const float4 vz = q[(ph + R + k + Q) % Q];
+                    const float4 vy = k == 0 ? ctr : t[(R + ty + k) * LW4 + tx + 1];
+                    const float ck = c[R + k];
+                    o[0] = fmaf(ck, vz.x + vy.x, o[0]);
+                    o[1] = fmaf(ck, vz.y + vy.y, o[1]);
+                    o[2] = fmaf(ck, vz.z + vy.z, o[2]);
+                    o[3] = fmaf(ck, vz.w + vy.w, o[3]);
+                }
+                {
                     const float4 L = t[(R + ty) * LW4 + tx];
                     const float4 Rr = t[(R + ty) * LW4 + tx + 2];
                     const float w[12] = {L.x,   L.y,   L.z,   L.w,  ctr.x, ctr.y,
@@ -234,9 +225,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
 #pragma unroll
                     for (int k = -R; k <= R; ++k)
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) s[e] = fmaf(c[R + k], w[4 + e + k], s[e]);
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) o[f][e] = s[e];
+                        for (int e = 0; e < 4; ++e) o[e] = fmaf(c[R + k], w[4 + e + k], o[e]);
                 }
                 const float gz = gaxis(z, g.nz, W, sa, zlo, zhi);
                 const bool live = lane_on && y < g.ny && x0 < g.nx;
@@ -244,15 +233,14 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                 float *po = a.out ? a.out + (int64_t)z * sz + own_off : nullptr;
                 const float p0v[4] = {pw0.x, pw0.y, pw0.z, pw0.w};
                 const float p1v[4] = {pw1.x, pw1.y, pw1.z, pw1.w};
-                const float4 ctr0 = q[0][(ph + R) % Q];
-                const float cv[4] = {ctr0.x, ctr0.y, ctr0.z, ctr0.w};
-                float r[4];
+                const float cv[4] = {ctr.x, ctr.y, ctr.z, ctr.w};
+                float r[4] = {0.f, 0.f, 0.f, 0.f};
                 if constexpr (MODE == MODE_FWD) {
                     // p0 = u^{n-1}, p1 = C2, ctr = u^n
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const float G = gz * gown[e];
-                        r[e] = G * (2.0f * cv[e] - G * p0v[e] + a.c2s * p1v[e] * o[0][e]);
+                        r[e] = G * (2.0f * cv[e] - G * p0v[e] + a.c2s * p1v[e] * o[e]);
                     }
                     if (srcv != 0.f && z == a.src_z && y == a.src_y && a.src_x >= x0 &&
                         a.src_x < x0 + 4) {
@@ -266,23 +254,25 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const float G = gz * gown[e];
-                        r[e] = 2.0f * G * p1v[e] - G * G * p0v[e] + o[0][e];
+                        r[e] = 2.0f * G * p1v[e] - G * G * p0v[e] + o[e];
                         if (rs && live && x0 + e < g.nx) r[e] += rs[e];
                     }
-                } else {
+                } else if constexpr (MODE == MODE_ENERGY) {
                     // ENERGY: p0 = u^{n+1}, p1 = C2, ctr = u^n, o = S u^n
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         if (live && x0 + e < g.nx) {
                             const double d = (double)p0v[e] - (double)cv[e];
-                            double t = -(double)p0v[e] * (double)o[0][e];
+                            double t = -(double)p0v[e] * (double)o[e];
                             if (p1v[e] != 0.f) t += d * d / ((double)a.c2s * (double)p1v[e]);
                             esum += t;
                         }
                     }
                 }
                 if (MODE != MODE_ENERGY && live) {
-                    if (x0 + 3 < g.nx) {
+                    if (MODE == MODE_GRAD) {
+                        // no field output
+                    } else if (x0 + 3 < g.nx) {
                         // streaming store: the next step reads this field from HBM anyway
                         const f4v v = {r[0], r[1], r[2], r[3]};
                         __builtin_nontemporal_store(v, reinterpret_cast<f4v *>(po));
@@ -315,8 +305,9 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                                         else
                                             *pp = sum;
                                     }
-                                } else if constexpr (GRAD) {
-                                    const float t = a.c2s * gz * gown[e] * p1v[e] * o[NF - 1][e];
+                                } else if constexpr (MODE == MODE_GRAD) {
+                                    // p0 = lam^{n+1}, o = S u^n
+                                    const float t = a.c2s * gz * gown[e] * p0v[e] * o[e];
                                     if (!a.part) {
                                         pa[e] += (double)t;
                                     } else {
@@ -334,8 +325,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                 }
                 if (more) {
                     ring_store((z + R + 1) % NR, nq, hreg);
-#pragma unroll
-                    for (int f = 0; f < NF; ++f) q[f][ph] = nq[f];
+                    q[ph] = nq;
                     pw0 = npw0;
                     pw1 = npw1;
                 }
@@ -404,34 +394,21 @@ __global__ void sum_partials_kernel(const double *p, int n, double *out) {
     if (threadIdx.x == 0) *out = s[0];
 }
 
-// Tile shapes: one stencil field -> 256 x 16 cells per block; two fields (adjoint with
-// gradient) -> 128 x 16.  Either way the LDS ring fills most of a CU's LDS, so one
-// block runs per CU.
-template <int MODE, bool GRAD>
-struct Cfg {
-    static constexpr bool TWO = MODE == MODE_ADJ && GRAD;
-    static constexpr int TX = TWO ? 32 : 64;
-    static constexpr int TY = 16;
-};
+// Tile shape: up to 256 x 16 cells per block (64 x 16 lanes); the LDS ring fills most
+// of a CU's LDS, so one block runs per CU.
+constexpr int WTX = 64, WTY = 16;
 
-template <int MODE, bool GRAD>
 void fill_geom(Geom &g, const mms_grid *gd) {
-    constexpr int TX = Cfg<MODE, GRAD>::TX, TY = Cfg<MODE, GRAD>::TY;
     g.H = gd->halo;
     g.nx = (int)gd->nx;
     g.ny = (int)gd->ny;
     g.nz = (int)gd->nz;
     g.sy = gd->sy;
     g.sz = gd->sz;
-    g.txa = balanced_tile_words(g.nx, TX, &g.ntx);
-    g.nty = (g.ny + TY - 1) / TY;
-    // one block per CU (LDS-bound).  The two-field adjoint fills two rings per
-    // block, so its chunk count follows the round model; the one-field kernels
-    // split the columns evenly over the CUs.
-    if (Cfg<MODE, GRAD>::TWO)
-        g.zchunk = pick_zchunk_rounds(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128, 10);
-    else
-        g.zchunk = pick_zchunk(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128);
+    g.txa = balanced_tile_words(g.nx, WTX, &g.ntx);
+    g.nty = (g.ny + WTY - 1) / WTY;
+    // one block per CU (LDS-bound): the columns split evenly over the CUs
+    g.zchunk = pick_zchunk(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128);
     g.nzc = (g.nz + g.zchunk - 1) / g.zchunk;
 }
 
@@ -448,18 +425,18 @@ WaveArgs base_args(const mms_wave *w) {
     return a;
 }
 
-template <int MODE, bool GRAD>
+template <int MODE>
 int launch_mode(WaveArgs &a, const mms_grid *gd, int r, hipStream_t s) {
-    constexpr int TX = Cfg<MODE, GRAD>::TX, TY = Cfg<MODE, GRAD>::TY;
-    fill_geom<MODE, GRAD>(a.g, gd);
+    constexpr int TX = WTX, TY = WTY;
+    fill_geom(a.g, gd);
     const int64_t nblk = (int64_t)a.g.ntx * a.g.nty * a.g.nzc;
     if (nblk > 0x7fffffff) return MMS_EINVAL;
     const dim3 grid((unsigned)nblk), block(TX * TY);
     switch (r) {
-        case 1: hipLaunchKernelGGL((wave_kernel<1, MODE, GRAD, TX, TY>), grid, block, 0, s, a); break;
-        case 2: hipLaunchKernelGGL((wave_kernel<2, MODE, GRAD, TX, TY>), grid, block, 0, s, a); break;
-        case 3: hipLaunchKernelGGL((wave_kernel<3, MODE, GRAD, TX, TY>), grid, block, 0, s, a); break;
-        case 4: hipLaunchKernelGGL((wave_kernel<4, MODE, GRAD, TX, TY>), grid, block, 0, s, a); break;
+        case 1: hipLaunchKernelGGL((wave_kernel<1, MODE, TX, TY>), grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL((wave_kernel<2, MODE, TX, TY>), grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL((wave_kernel<3, MODE, TX, TY>), grid, block, 0, s, a); break;
+        case 4: hipLaunchKernelGGL((wave_kernel<4, MODE, TX, TY>), grid, block, 0, s, a); break;
         default: return MMS_EUNSUPPORTED;
     }
     return check_launch("wave_kernel");
@@ -485,7 +462,7 @@ int wave_step(const mms_wave *w, int n, const float *up, const float *uc, float 
     a.src_z = (int)w->src_z;
     a.src_y = (int)w->src_y;
     a.src_x = (int)w->src_x;
-    return launch_mode<MODE_FWD, false>(a, &w->g, w->radius, s);
+    return launch_mode<MODE_FWD>(a, &w->g, w->radius, s);
 }
 
 int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1, float *l0,
@@ -496,26 +473,30 @@ int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1
     a.out = l0 + o;
     a.resid = resid ? resid + (int64_t)n * w->g.ny * w->g.nx : nullptr;
     if (n == 0) {
-        fill_geom<MODE_ADJ, false>(a.g, &w->g);
+        fill_geom(a.g, &w->g);
         const int64_t np = w->g.nx * w->g.ny * w->g.nz;
         const unsigned nb = (unsigned)((np + 255) / 256);
         hipLaunchKernelGGL(adjoint_first_kernel, dim3(nb), dim3(256), 0, s, a);
         return check_launch("adjoint_first_kernel");
     }
     a.f0 = l1 + o;
-    if (grad) {
-        a.fu = un + o;
-        a.acc64 = grad;
-        if (w->acc_block > 1) {
-            // blocks counted down from n = nt-1, the order the adjoint runs in
-            const int K = w->acc_block, ph = (w->nt - 1 - n) % K;
-            a.part = w->acc_part;
-            a.part_first = ph == 0;
-            a.part_last = ph == K - 1 || n == 1;
-        }
-        return launch_mode<MODE_ADJ, true>(a, &w->g, w->radius, s);
+    const int rc = launch_mode<MODE_ADJ>(a, &w->g, w->radius, s);
+    if (rc || !grad) return rc;
+    // gradient: a second one-field pass over u^n (stencil) and lam^{n+1}.  Fused into
+    // the adjoint pass it needs two register queues and two LDS rings, which halves
+    // the tile and the occupancy; two passes move 6 B more per point and run faster.
+    WaveArgs b = base_args(w);
+    b.f0 = un + o;
+    b.p0 = l1 + o;
+    b.acc64 = grad;
+    if (w->acc_block > 1) {
+        // blocks counted down from n = nt-1, the order the adjoint runs in
+        const int K = w->acc_block, ph = (w->nt - 1 - n) % K;
+        b.part = w->acc_part;
+        b.part_first = ph == 0;
+        b.part_last = ph == K - 1 || n == 1;
     }
-    return launch_mode<MODE_ADJ, false>(a, &w->g, w->radius, s);
+    return launch_mode<MODE_GRAD>(b, &w->g, w->radius, s);
 }
 
 int wave_record(const mms_wave *w, int n, const float *u, hipStream_t s) {
@@ -542,10 +523,10 @@ int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *o
     a.f0 = un + o;
     a.p0 = unp1 + o;
     a.partials = partials;
-    fill_geom<MODE_ENERGY, false>(a.g, &w->g);
+    fill_geom(a.g, &w->g);
     const int64_t nblk = (int64_t)a.g.ntx * a.g.nty * a.g.nzc;
     if (nblk > npartials) return MMS_ENOMEM;
-    int rc = launch_mode<MODE_ENERGY, false>(a, &w->g, w->radius, s);
+    int rc = launch_mode<MODE_ENERGY>(a, &w->g, w->radius, s);
     if (rc) return rc;
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partials, (int)nblk, out);
     return check_launch("sum_partials_kernel");
@@ -553,7 +534,7 @@ int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *o
 
 int64_t wave_energy_blocks(const mms_wave *w) {
     Geom g{};
-    fill_geom<MODE_ENERGY, false>(g, &w->g);
+    fill_geom(g, &w->g);
     return (int64_t)g.ntx * g.nty * g.nzc;
 }
 
