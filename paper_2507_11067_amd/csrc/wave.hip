@@ -288,35 +288,70 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                             if (x0 + e < g.nx) pt[e] = cv[e];
                     }
                     if (a.acc64) {
-                        double *pa = a.acc64 + dense;
+                        // the accumulated term of each cell: FWD (u^{n+1})^2, GRAD
+                        // G lam^{n+1} S(u^n) (p0 = lam^{n+1}, o = S u^n); in FP32 for the
+                        // block partial, in FP64 for a direct update
+                        float t[4];
+                        double t64[4];
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
-                            if (x0 + e < g.nx) {
-                                if constexpr (MODE == MODE_FWD) {
-                                    if (!a.part) {
-                                        pa[e] += (double)r[e] * (double)r[e];
-                                    } else {
-                                        // FP32 partial over the block, added in FP64 at its end
-                                        float *pp = a.part + dense + e;
-                                        const float t = r[e] * r[e];
-                                        const float sum = a.part_first ? t : *pp + t;
+                            if constexpr (MODE == MODE_FWD) {
+                                t[e] = r[e] * r[e];
+                                t64[e] = (double)r[e] * (double)r[e];
+                            } else {
+                                t[e] = a.c2s * gz * gown[e] * p0v[e] * o[e];
+                                t64[e] = (double)t[e];
+                            }
+                        }
+                        double *pa = a.acc64 + dense;
+                        // four cells in range on a 16-byte aligned dense row: one 16-byte
+                        // access per operand (two for the FP64 sums) instead of four
+                        const bool vec = x0 + 3 < g.nx && (dense & 3) == 0;
+                        if (!a.part) {
+                            if (vec) {
+                                double2 *p2 = reinterpret_cast<double2 *>(pa);
+                                double2 lo = p2[0], hi = p2[1];
+                                lo.x += t64[0];
+                                lo.y += t64[1];
+                                hi.x += t64[2];
+                                hi.y += t64[3];
+                                p2[0] = lo;
+                                p2[1] = hi;
+                            } else {
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    if (x0 + e < g.nx) pa[e] += t64[e];
+                            }
+                        } else {
+                            // FP32 partial over the block, added in FP64 at its end
+                            float *pp = a.part + dense;
+                            if (vec) {
+                                const float4 pv = a.part_first ? zero4 : *reinterpret_cast<const float4 *>(pp);
+                                const float pa4[4] = {pv.x, pv.y, pv.z, pv.w};
+                                float sum[4];
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) sum[e] = a.part_first ? t[e] : pa4[e] + t[e];
+                                if (a.part_last) {
+                                    double2 *p2 = reinterpret_cast<double2 *>(pa);
+                                    double2 lo = p2[0], hi = p2[1];
+                                    lo.x += (double)sum[0];
+                                    lo.y += (double)sum[1];
+                                    hi.x += (double)sum[2];
+                                    hi.y += (double)sum[3];
+                                    p2[0] = lo;
+                                    p2[1] = hi;
+                                } else {
+                                    *reinterpret_cast<float4 *>(pp) = make_float4(sum[0], sum[1], sum[2], sum[3]);
+                                }
+                            } else {
+#pragma unroll
+                                for (int e = 0; e < 4; ++e) {
+                                    if (x0 + e < g.nx) {
+                                        const float sum = a.part_first ? t[e] : pp[e] + t[e];
                                         if (a.part_last)
                                             pa[e] += (double)sum;
                                         else
-                                            *pp = sum;
-                                    }
-                                } else if constexpr (MODE == MODE_GRAD) {
-                                    // p0 = lam^{n+1}, o = S u^n
-                                    const float t = a.c2s * gz * gown[e] * p0v[e] * o[e];
-                                    if (!a.part) {
-                                        pa[e] += (double)t;
-                                    } else {
-                                        float *pp = a.part + dense + e;
-                                        const float sum = a.part_first ? t : *pp + t;
-                                        if (a.part_last)
-                                            pa[e] += (double)sum;
-                                        else
-                                            *pp = sum;
+                                            pp[e] = sum;
                                     }
                                 }
                             }
