@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
     constexpr int Q = 2 * R + 1;
     constexpr int S = Q + 3;         // queue slots (even)
     constexpr int NR = R + 2;        // LDS ring planes
-    constexpr int BX = 4 * TX, BY = TY;
+    constexpr int BY = TY;
     constexpr int LW4 = TX + 2, LH = BY + 2 * R;
     constexpr int NT = TX * TY;
     constexpr int NH = 2 * R * LW4 + 2 * BY;
@@ -60,7 +60,11 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
     const int zci = b / g.nty;
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    const int xt = txi * BX, yt = tyi * BY;
+    // balanced x tiles: txa <= TX lanes of each row own words, the rest only help
+    // with the halo and the barriers
+    const int txa = g.txa, lw = txa + 2, bxa = 4 * txa;
+    const bool lane_on = tx < txa;
+    const int xt = txi * bxa, yt = tyi * BY;
     const int x0 = xt + 4 * tx, y0 = yt + ty;
     const int zb = zci * g.zchunk;
     const int ze = min(zb + g.zchunk, g.nz);
@@ -70,29 +74,30 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
     const float *in0 = g.in0;
     const int64_t sy = g.sy, sz = g.sz;
 
-    const bool own_ok = (x0 <= nx4) && (y0 < ylim);
+    const bool own_ok = lane_on && (x0 <= nx4) && (y0 < ylim);
     const int64_t own_off = (int64_t)y0 * sy + x0;
     int64_t h_off[NHK];
     int h_lds[NHK];
-    bool h_ok[NHK];
+    bool h_ok[NHK], h_on[NHK];  // h_on: item k is one of this tile's halo words
 #pragma unroll
     for (int k = 0; k < NHK; ++k) {
         const int i = tid + k * NT;
         int row, lrow, col4, x;
-        if (i < 2 * R * LW4) {
-            const int hr = i / LW4, hc = i % LW4;
+        if (i < 2 * R * lw) {
+            const int hr = i / lw, hc = i % lw;
             row = hr < R ? yt - R + hr : yt + BY + (hr - R);
             lrow = hr < R ? hr : hr + BY;
             col4 = hc;
             x = xt - 4 + 4 * hc;
         } else {
-            const int j = i - 2 * R * LW4;
+            const int j = i - 2 * R * lw;
             row = yt + j / 2;
             lrow = R + j / 2;
-            col4 = (j & 1) ? LW4 - 1 : 0;
-            x = (j & 1) ? xt + BX : xt - 4;
+            col4 = (j & 1) ? txa + 1 : 0;
+            x = (j & 1) ? xt + bxa : xt - 4;
         }
-        h_ok[k] = (i < NH) && (row < ylim) && (x <= nx4);
+        h_on[k] = i < 2 * R * lw + 2 * BY;
+        h_ok[k] = h_on[k] && (row < ylim) && (x <= nx4);
         h_off[k] = (int64_t)row * sy + x;
         h_lds[k] = lrow * LW4 + col4;
     }
@@ -104,10 +109,10 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
     };
     auto ring_store = [&](int z, const float4 &own, const float4 *halo) {
         float4 *t = &ring[z % NR][0][0];
-        t[(R + ty) * LW4 + tx + 1] = own;
+        if (lane_on) t[(R + ty) * LW4 + tx + 1] = own;
 #pragma unroll
         for (int k = 0; k < NHK; ++k)
-            if (tid + k * NT < NH) t[h_lds[k]] = halo[k];
+            if (h_on[k]) t[h_lds[k]] = halo[k];
     };
 
     float4 q[S];
@@ -171,7 +176,7 @@ __global__ void __launch_bounds__(TX *TY) star_kernel(StarArgs a) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) o[e] = fmaf(ck, w[4 + e + k], o[e]);
         }
-        if (y0 < g.ny && x0 < g.nx) {
+        if (lane_on && y0 < g.ny && x0 < g.nx) {
             float *po = out0 + (int64_t)z * sz + own_off;
             if (x0 + 3 < g.nx) {
                 const f4v v = {o[0], o[1], o[2], o[3]};
@@ -211,7 +216,7 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     g.nz = (int)gd->nz;
     g.sy = gd->sy;
     g.sz = gd->sz;
-    g.ntx = (g.nx + 4 * TX - 1) / (4 * TX);
+    g.txa = balanced_tile_words(g.nx, TX, &g.ntx);
     g.nty = (g.ny + TY - 1) / TY;
     int zc = zchunk_override(MMS_STAR, MMS_FP32);
     if (zc <= 0) {
