@@ -681,7 +681,7 @@ COUNTED = {
     "box4": ("box_valu.hip", "box_valu_kernel<4", 8.0),
     "box4_bf16x3": ("box_mfma.hip", "box_mfma_kernel<4, 1,", 8.0),
     "box3_bf16x3": ("box_mfma.hip", "box_mfma_kernel<3, 1,", 8.0),
-    "wave": ("wave.hip", "wave_kernel<4, 0, false", 16.0),   # 400^3 forward step, no image
+    "wave": ("wave.hip", "wave_kernel<4, 0, 64", 16.0),   # 400^3 forward step, no image
     "vti": ("vti.hip", "vti_kernel<4", 36.0),                # 400^3 VTI step
     "tti_dz": ("tti.hip", "tti_dz_kernel<4", 24.0),          # 400^3 TTI pass 1 (padded rows)
     "tti": ("tti.hip", "tti_kernel<4", 60.0),                # 400^3 TTI pass 2
@@ -788,7 +788,7 @@ def collect_counters(args):
 
     summary = {"kernels": {}, "commands": {}}
     # 1. kernel trace of the headline command
-    targs = ["--steps", "20", "--warmup", "2", "--skip", "split,table1,rtm,vti,tti,gradient,cpu,check"]
+    targs = ["--steps", "60", "--warmup", "40", "--skip", "split,table1,rtm,vti,tti,gradient,cpu,check"]
     d, cmd = prof("trace_headline", ["--kernel-trace", "--stats"], targs, 300)
     stats = find(d, "_kernel_stats.csv")
     summary["commands"]["trace_headline"] = cmd
@@ -800,7 +800,7 @@ def collect_counters(args):
     summary["trace_only"] = {}
     for name in ("box4_bf16x3", "box3_bf16x3", "wave", "vti", "tti_dz", "tti"):
         d, cmd = prof(f"trace_{name}", ["--kernel-trace", "--stats"],
-                      ["--only", COUNTED_ONLY.get(name, name), "--steps", "20", "--warmup", "2"],
+                      ["--only", COUNTED_ONLY.get(name, name), "--steps", "200", "--warmup", "40"],
                       120)
         ns, calls = _stats_mean_ns(find(d, "_kernel_stats.csv"), COUNTED[name][1])
         summary["trace_only"][name] = {"avg_ns": ns, "calls": calls, "command": cmd,
