@@ -234,6 +234,18 @@ def main():
                                "unit": "TFLOP/s", "frac": k["valu_frac"],
                                "traffic": traffic_for(name)}
 
+    # context for the HBM-bound rows: what a plain device copy of the same padded grid
+    # moves on this GPU (read + write), timed the same way
+    cms = time_launches(torch, lambda: outs["box2"].copy_(x))
+    copy_gbs = 2.0 * x.numel() * 4 / (cms * 1e-3) / 1e9
+    rooflines["star"]["copy_gbs"] = copy_gbs
+    rooflines["star"]["frac_of_copy"] = kernels["star"]["gbs"] / copy_gbs
+    if rooflines["star"]["traffic"]:
+        # bytes the counters saw per sweep, over the live sweep time
+        rooflines["star"]["traffic_gbs"] = rooflines["star"]["traffic"] / (kernels["star"]["ms"] * 1e-3) / 1e9
+    log(f"[bench] plain copy of the padded grid: {copy_gbs:.0f} GB/s; star at "
+        f"{kernels['star']['gbs'] / copy_gbs:.2f} of it (algorithmic bytes)")
+
     result = {
         "metric": METRIC, "value": value, "unit": "Gpoints/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
