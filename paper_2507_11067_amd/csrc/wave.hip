@@ -175,9 +175,17 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
         ring_store((zb + i) % NR, q[R + i], hreg);
     }
     // point-wise operands of the first plane
-    // second point-wise operand: lam^{n+1} (ADJ), C2 (FWD, ENERGY), none (GRAD)
+    // second point-wise operand: lam^{n+1} (ADJ), C2 (FWD, ENERGY); GRAD: the FP32 block
+    // partial of the lane's cells (when it is read and the row allows 16-byte access)
     auto ld_pw1 = [&](int z) -> float4 {
-        if constexpr (MODE == MODE_GRAD) return zero4;
+        if constexpr (MODE == MODE_GRAD) {
+            // the same condition as the 16-byte path of the accumulation below
+            // (otherwise the load reads the interior origin of C2 and the value is unused)
+            const int64_t d = ((int64_t)z * g.ny + y) * g.nx + x0;
+            const bool use = a.part && !a.part_first && lane_on && y < g.ny && x0 + 3 < g.nx &&
+                             (d & 3) == 0;
+            return *reinterpret_cast<const float4 *>(use ? a.part + d : a.c2);
+        }
         return ld(MODE == MODE_ADJ ? a.f0 : a.c2, z, own_off, own_ok);
     };
     float4 pw0 = ld(a.p0, zb, own_off, own_ok);
@@ -193,7 +201,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
             if (z < ze) {
                 const bool more = z + 1 < ze;
                 float4 nq = zero4;
-                float4 npw0 = zero4, npw1 = zero4;
+                float4 npw0 = pw0, npw1 = pw1;   // replaced below unless this is the last plane
                 if (more) {
                     // the tile of plane z+R+1 is requested together with the neighbouring
                     // tiles that read the same rows, and parked in the ring
@@ -287,22 +295,17 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                         for (int e = 0; e < 4; ++e)
                             if (x0 + e < g.nx) pt[e] = cv[e];
                     }
-                    if (a.acc64) {
+                    if (MODE == MODE_FWD || MODE == MODE_GRAD) if (a.acc64) {
                         // the accumulated term of each cell: FWD (u^{n+1})^2, GRAD
                         // G lam^{n+1} S(u^n) (p0 = lam^{n+1}, o = S u^n); in FP32 for the
-                        // block partial, in FP64 for a direct update
+                        // block partial, in FP64 for a direct update (t64)
                         float t[4];
-                        double t64[4];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            if constexpr (MODE == MODE_FWD) {
-                                t[e] = r[e] * r[e];
-                                t64[e] = (double)r[e] * (double)r[e];
-                            } else {
-                                t[e] = a.c2s * gz * gown[e] * p0v[e] * o[e];
-                                t64[e] = (double)t[e];
-                            }
-                        }
+                        for (int e = 0; e < 4; ++e)
+                            t[e] = MODE == MODE_FWD ? r[e] * r[e] : a.c2s * gz * gown[e] * p0v[e] * o[e];
+                        auto t64 = [&](int e) -> double {
+                            return MODE == MODE_FWD ? (double)r[e] * (double)r[e] : (double)t[e];
+                        };
                         double *pa = a.acc64 + dense;
                         // four cells in range on a 16-byte aligned dense row: one 16-byte
                         // access per operand (two for the FP64 sums) instead of four
@@ -311,22 +314,25 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                             if (vec) {
                                 double2 *p2 = reinterpret_cast<double2 *>(pa);
                                 double2 lo = p2[0], hi = p2[1];
-                                lo.x += t64[0];
-                                lo.y += t64[1];
-                                hi.x += t64[2];
-                                hi.y += t64[3];
+                                lo.x += t64(0);
+                                lo.y += t64(1);
+                                hi.x += t64(2);
+                                hi.y += t64(3);
                                 p2[0] = lo;
                                 p2[1] = hi;
                             } else {
 #pragma unroll
                                 for (int e = 0; e < 4; ++e)
-                                    if (x0 + e < g.nx) pa[e] += t64[e];
+                                    if (x0 + e < g.nx) pa[e] += t64(e);
                             }
                         } else {
                             // FP32 partial over the block, added in FP64 at its end
                             float *pp = a.part + dense;
                             if (vec) {
-                                const float4 pv = a.part_first ? zero4 : *reinterpret_cast<const float4 *>(pp);
+                                // GRAD: the partial came with the point-wise operands
+                                const float4 pv = a.part_first ? zero4
+                                                  : MODE == MODE_GRAD ? pw1
+                                                                      : *reinterpret_cast<const float4 *>(pp);
                                 const float pa4[4] = {pv.x, pv.y, pv.z, pv.w};
                                 float sum[4];
 #pragma unroll
