@@ -54,7 +54,7 @@ def smooth(seed, grid):
     return synth.smooth_random_grid(seed, grid.nx, grid.ny, grid.nz)
 
 
-@pytest.mark.parametrize("dims", [(20, 20, 20), (37, 19, 11), (128, 8, 16)],
+@pytest.mark.parametrize("dims", [(20, 20, 20), (37, 19, 11), (128, 8, 16), (300, 9, 13)],
                          ids=lambda d: "x".join(map(str, d)))
 def test_forward_step_parity(mms, dims):
     nx, ny, nz = dims
@@ -86,9 +86,11 @@ def test_forward_step_parity(mms, dims):
     assert abs(got[src[0] + 4, src[1] + 4, src[2] + 4]) > 0
 
 
-@pytest.mark.parametrize("n_step", [0, 1, 6])
-def test_adjoint_step_parity(mms, n_step):
-    nx, ny, nz = 30, 22, 18
+@pytest.mark.parametrize("n_step,dims", [(0, (30, 22, 18)), (1, (30, 22, 18)), (6, (30, 22, 18)),
+                                         (6, (300, 9, 13))],
+                         ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else str(v))
+def test_adjoint_step_parity(mms, n_step, dims):
+    nx, ny, nz = dims
     nt = 10
     grid, c2, f, src, _ = setup_small(mms, nx, nt, 4, ny=ny, nz=nz)
     l2, l1, un = smooth(5, grid), smooth(6, grid), smooth(7, grid)
@@ -309,3 +311,36 @@ def test_gradient_vs_oracle_64(mms):
           f"J {J.item():.6e} vs {J_ref:.6e}")
     assert rmax <= 1e-3
     assert J.item() == pytest.approx(J_ref, rel=1e-3)
+
+
+@pytest.mark.parametrize("nx", [300, 301])
+def test_blocked_accumulation_wide_rows(mms, nx):
+    """Rows split over two x tiles (300 cells: 2 x 38 words) and rows whose dense offsets are
+    not 16-byte aligned (301): image and gradient summed in blocks of 4 steps against every
+    step added in FP64."""
+    ny, nz, nt, K = 9, 13, 10, 4
+    grid, c2, f, src, _ = setup_small(mms, nx, nt, 17, ny=ny, nz=nz)
+    lam = [T(smooth(20 + i, grid)) for i in range(nt + 2)]
+    us = [T(smooth(40 + i, grid)) for i in range(nt)]
+    resid = T(np.random.default_rng(18).standard_normal((nt, ny, nx)))
+    images, grads = [], []
+    for block in (1, K):
+        part = torch.full((nz, ny, nx), 3.0, device=DEV)   # stale contents are overwritten
+        image = torch.zeros((nz, ny, nx), dtype=torch.float64, device=DEV)
+        w = gpu_wave(mms, grid, T(c2), T(f), src, nt, 4)
+        w.set_image(image, part if block > 1 else None, block)
+        bufs = [grid.zeros(DEV) for _ in range(3)]
+        w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+        grad = torch.zeros((nz, ny, nx), dtype=torch.float64, device=DEV)
+        w.set_accumulation(part if block > 1 else None, block)
+        out = grid.zeros(DEV)
+        for n in range(nt - 1, 0, -1):       # the order the adjoint runs in
+            w.adjoint_step(n, lam[n + 2], lam[n + 1], out, resid=resid, u_n=us[n], grad=grad)
+        torch.cuda.synchronize()
+        images.append(image.cpu().numpy())
+        grads.append(grad.cpu().numpy())
+    ri, _ = rel_errors(images[1], images[0])
+    rg, _ = rel_errors(grads[1], grads[0])
+    print(f"nx {nx}: blocked vs per-step image {ri:.2e}, gradient {rg:.2e}")
+    assert np.abs(images[0]).max() > 0 and np.abs(grads[0]).max() > 0
+    assert ri <= 1e-6 and rg <= 1e-6
