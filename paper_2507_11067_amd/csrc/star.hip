@@ -3,7 +3,8 @@
 // out(p) = sum_{axis a} sum_{k=-r..r} c[a][k+r] in(p + k e_a)   (Sec. I, Fig. 1)
 //
 // The sweep is bound by HBM: 4 bytes read and 4 written per point.  Each block
-// owns a (4*TX) x TY tile of the (x, y) plane and streams a chunk of z planes
+// owns a (4*txa) x TY tile of the (x, y) plane (txa <= TX lanes per row, the same
+// for every tile of a row: balanced x tiles) and streams a chunk of z planes
 // through it:
 //  * every lane owns 4 consecutive x (one 16-byte load) of one row and keeps the
 //    z planes of those cells in a register queue, so the z-axis terms never
