@@ -65,6 +65,8 @@ def parse():
     p.add_argument("--collect", action="store_true",
                    help="run rocprofv3 (kernel trace, FETCH_SIZE, WRITE_SIZE) as child processes "
                         "over the headline kernels and a plain copy, and write profiles/")
+    p.add_argument("--collect-dir", default=os.path.join(ROOT, "rocprof_out"),
+                   help="where --collect puts the raw rocprofv3 output and a copy of the summaries")
     return p.parse_args()
 
 
@@ -775,7 +777,7 @@ def collect_counters(args):
     The copy kernel of known size calibrates each counter: bytes = counter * factor."""
     import glob
     import subprocess
-    out_root = os.path.join(ROOT, "gpurun_out", "counters")
+    out_root = os.path.abspath(args.collect_dir)
     os.makedirs(out_root, exist_ok=True)
     py = sys.executable
 
