@@ -537,7 +537,8 @@ def bench_gradient(torch, mms, synth, dev, n=256, nt=1000, K=50):
     res = {"grid": [n, n, n], "steps": nt - 1, "checkpoint_every": K, "J": float(J.item()),
            "forward_ms": fwd_ms, "backward_ms": bwd_ms,
            "gpoints_s": pts / ((fwd_ms + bwd_ms) * 1e-3) / 1e9,
-           "recomputed_steps": prob.stats.get("recomputed_steps")}
+           "recomputed_steps": prob.stats.get("recomputed_steps"),
+           "adjoint_form": prob.stats.get("adjoint_form")}
     log(f"[bench] gradient: fwd {fwd_ms:.0f} ms, bwd {bwd_ms:.0f} ms")
     # dot-product test of the adjoint at the full size: A (u0, u1) -> traces (no source),
     # tested against y = the misfit residual of the gradient run (a smooth trace field)
@@ -555,7 +556,16 @@ def bench_gradient(torch, mms, synth, dev, n=256, nt=1000, K=50):
     lhs = mms.flat_dot(w.traces, y)
     rhs = mms.dot(u0, lam[0], grid) + mms.dot(u1, lam[1], grid)
     res["dot_test"] = {"lhs": lhs, "rhs": rhs, "rel": abs(lhs - rhs) / abs(lhs)}
-    log(f"[bench] dot test rel {res['dot_test']['rel']:.2e}")
+    # the same identity with the adjoint carried in mu = C2 G lam
+    for b_ in lam:
+        b_.zero_()
+    w.adjoint_mu(nt - 1, 0, [lam[i % 3] for i in range(nt + 2)], resid=y)
+    w.scale_mu(lam[0], lam[0], -1)
+    w.scale_mu(lam[1], lam[1], -1)
+    rhs_mu = mms.dot(u0, lam[0], grid) + mms.dot(u1, lam[1], grid)
+    res["dot_test_mu"] = {"lhs": lhs, "rhs": rhs_mu, "rel": abs(lhs - rhs_mu) / abs(lhs)}
+    log(f"[bench] dot test rel {res['dot_test']['rel']:.2e} (lam), "
+        f"{res['dot_test_mu']['rel']:.2e} (mu)")
     res["finite_differences"], res["taylor"] = gradient_checks(torch, mms, synth, prob, m, d_obs,
                                                                grid, dev)
     return res

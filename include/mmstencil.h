@@ -226,6 +226,30 @@ int mms_tti_step(const mms_wave *w, const mms_tti *t, int n, const float *p_prev
                  float *q_next, void *stream);
 
 /*
+ * mms_wave_adjoint_mu -- the steps n_hi .. n_lo of mms_wave_adjoint carried in the
+ * scaled variable mu = C2 G lam (C2 = c2_scale c2, G the sponge factor).  The exact
+ * discrete adjoint of the previous section then has the forward step's form, with one
+ * stencil operand:
+ *   mu^n = G (2 mu^{n+1} - G mu^{n+2} + C2 S(mu^{n+1})) + C2 G R^T resid[n]   (n >= 1)
+ *   mu^0 = -G^2 mu^2 + C2 G R^T resid[0]
+ * mus[i] holds mu^{n_lo+i}; entries n_hi-n_lo+1 and n_hi-n_lo+2 are inputs, the rest are
+ * outputs (a HOST array of device pointers; entries may repeat as in mms_wave_adjoint).
+ * With grad: grad += c2_scale G lam^{n+1} S(u^n) for n = max(n_lo, 1) .. n_hi, the same
+ * terms as mms_wave_adjoint, formed as mu^{n+1} S(u^n) / c2; acc_block blocks as there.
+ * Requires c2 > 0 in every interior cell (lam = mu / (C2 G)); results are undefined
+ * otherwise.  Buffers are checked before anything is enqueued.
+ */
+int mms_wave_adjoint_mu(const mms_wave *w, int n_hi, int n_lo, float *const *mus,
+                        const float *const *us, const float *resid, double *grad, void *stream);
+
+/*
+ * mms_wave_scale_mu -- out = C2 G in (dir = +1: lam -> mu) or out = in / (C2 G)
+ * (dir = -1: mu -> lam) on the interior; out may equal in, and must not otherwise
+ * overlap it.  Halo cells of out are left unchanged.  dir = -1 requires c2 > 0.
+ */
+int mms_wave_scale_mu(const mms_wave *w, const float *in, float *out, int dir, void *stream);
+
+/*
  * mms_wave_energy -- FP64 discrete energy of the leapfrog scheme without
  * sponge or source, E^{n+1/2} = sum (u^{n+1}-u^n)^2 / C2 - <u^{n+1}, S u^n>,
  * which the scheme conserves exactly for a symmetric S.  *out_dev (device) is

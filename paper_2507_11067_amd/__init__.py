@@ -206,6 +206,28 @@ class Wave:
             _dev_ptr(resid, "resid", torch.float32, self.nt * g.ny * g.nx),
             _dev_ptr(grad, "grad", torch.float64, g.points), _stream(stream)), "mms_wave_adjoint")
 
+    def adjoint_mu(self, n_hi, n_lo, mus, us=None, resid=None, grad=None, stream=None):
+        """Adjoint steps n_hi..n_lo in the variable mu = C2 G lam (see mms_wave_adjoint_mu);
+        mus[i] is mu^{n_lo+i}, us[i] is u^{n_lo+i}.  Needs c2 > 0 in every cell."""
+        g = self.grid
+        if len(mus) < n_hi - n_lo + 3:
+            raise ValueError("mus too short")
+        ma = (ctypes.c_void_p * len(mus))(*[_grid_ptr(t, g, "mu") for t in mus])
+        ua = None
+        if us is not None:
+            ua = (ctypes.c_void_p * len(us))(*[_grid_ptr(t, g, "u") for t in us])
+        check(lib().mms_wave_adjoint_mu(
+            ctypes.byref(self._w), int(n_hi), int(n_lo), ma, ua,
+            _dev_ptr(resid, "resid", torch.float32, self.nt * g.ny * g.nx),
+            _dev_ptr(grad, "grad", torch.float64, g.points), _stream(stream)), "mms_wave_adjoint_mu")
+
+    def scale_mu(self, inp, out, direction, stream=None):
+        """out = C2 G inp (direction +1, lam -> mu) or inp / (C2 G) (direction -1)."""
+        g = self.grid
+        check(lib().mms_wave_scale_mu(ctypes.byref(self._w), _grid_ptr(inp, g, "in"),
+                                      _grid_ptr(out, g, "out"), int(direction), _stream(stream)),
+              "mms_wave_scale_mu")
+
     def vti_step(self, n, a, b, h_prev, h_cur, h_next, v_prev, v_cur, v_next, stream=None):
         """One pseudo-acoustic VTI step (see mms_vti_step); a = 1 + 2 eps, b = sqrt(1 + 2 delta)."""
         g = self.grid

@@ -4,8 +4,10 @@ adjoint wave kernels (torch.autograd.Function), with checkpoint/recompute.
 WavePropagate.apply(m, u0, u1, problem) -> traces [nt, ny, nx]
     m = v^2 on the padded grid (FP32); u0, u1 = the first two wavefield levels.
     Backward returns dJ/dm, dJ/du0, dJ/du1 for any loss J of the traces, from
-    the exact discrete adjoint (mms_wave_adjoint), not from a self-adjoint
-    shortcut.
+    the exact discrete adjoint, not from a self-adjoint shortcut.  Where m > 0
+    on the whole interior the adjoint runs in mu = C2 G lam
+    (mms_wave_adjoint_mu: the forward step's form, one fewer field stream per
+    step), otherwise in lam (mms_wave_adjoint).
 
 Memory plan: the forward pass keeps the pair (u^k, u^{k+1}) at every level
 k = 0, K, 2K, ... .  The backward pass walks the segments [k, k+K) from the
@@ -40,6 +42,7 @@ class Problem:
     sponge_faces: int = 0
     checkpoint_every: int = 50
     grad_block: int = 8        # adjoint steps whose gradient terms are summed in FP32
+    adjoint_form: str = "auto"  # "mu" (needs m > 0 on the interior), "lam", or "auto"
     stats: dict = field(default_factory=dict)
 
     @property
@@ -87,7 +90,15 @@ class WavePropagate(torch.autograd.Function):
         dev = m.device
         resid = grad_traces.detach().to(torch.float32).contiguous()
         wa = prob.wave(m, source=False)    # adjoint: geometry, C2 and sponge
-        lam = [g.zeros(dev) for _ in range(3)]   # lam^n lives in lam[n % 3]
+        H = g.halo
+        if prob.adjoint_form not in ("auto", "mu", "lam"):
+            raise ValueError(f"adjoint_form {prob.adjoint_form!r}")
+        positive = prob.adjoint_form != "lam" and bool((m[H:H + g.nz, H:H + g.ny, H:H + g.nx] > 0).all())
+        if prob.adjoint_form == "mu" and not positive:
+            raise ValueError("adjoint_form 'mu' needs m > 0 on the whole interior")
+        mu_form = positive
+        adjoint = wa.adjoint_mu if mu_form else wa.adjoint
+        lam = [g.zeros(dev) for _ in range(3)]   # lam^n (or mu^n) lives in lam[n % 3]
         seg = [g.zeros(dev) for _ in range(min(K, max(nt, 1)))]
         grad = torch.zeros((g.nz, g.ny, g.nx), dtype=torch.float64, device=dev)
         if prob.grad_block > 1:
@@ -104,12 +115,16 @@ class WavePropagate(torch.autograd.Function):
             if hi >= k + 2:
                 w_src.forward(k + 1, hi, seg[0:hi - k + 1])
                 recomputed += hi - k - 1
-            wa.adjoint(hi, k, [lam[(k + i) % 3] for i in range(hi - k + 3)],
-                       us=seg[0:hi - k + 1], resid=resid, grad=grad)
+            adjoint(hi, k, [lam[(k + i) % 3] for i in range(hi - k + 3)],
+                    us=seg[0:hi - k + 1], resid=resid, grad=grad)
+        if mu_form:
+            for b in lam[:2]:
+                wa.scale_mu(b, b, -1)      # mu^0, mu^1 -> lam^0, lam^1
         grad_m = dense_to_grid(grad, g.zeros(dev), g)
         grad_u0 = lam[0].clone() if nt > 0 else g.zeros(dev)
         grad_u1 = lam[1 % 3].clone() if nt > 1 else g.zeros(dev)
         prob.stats["recomputed_steps"] = recomputed
+        prob.stats["adjoint_form"] = "mu" if mu_form else "lam"
         ctx.ckpts = None
         return grad_m, grad_u0, grad_u1, None
 

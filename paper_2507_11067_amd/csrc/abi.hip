@@ -14,6 +14,10 @@ int wave_step(const mms_wave *w, int n, const float *up, const float *uc, float 
 int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1, float *l0,
                       const float *resid, const float *un, double *grad, hipStream_t s);
 int wave_record(const mms_wave *w, int n, const float *u, hipStream_t s);
+int wave_adjoint_mu_step(const mms_wave *w, int n, const float *m2, const float *m1, float *m0,
+                         const float *resid, const float *un, double *grad, hipStream_t s);
+int wave_scale_mu(const mms_wave *w, const float *in, float *out, int dir, hipStream_t s);
+int wave_grad_c2(const mms_wave *w, double *grad, int dir, hipStream_t s);
 int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *out, double *partials,
                 int64_t npartials, hipStream_t s);
 int64_t wave_energy_blocks(const mms_wave *w);
@@ -278,6 +282,51 @@ int mms_wave_adjoint(const mms_wave *w, int n_hi, int n_lo, float *const *lams,
         if (rc) return rc;
     }
     return MMS_OK;
+}
+
+int mms_wave_adjoint_mu(const mms_wave *w, int n_hi, int n_lo, float *const *mus,
+                        const float *const *us, const float *resid, double *grad, void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!mus || n_lo < 0 || n_hi >= w->nt || n_hi < n_lo) return MMS_EINVAL;
+    if (grad && !us) return MMS_EINVAL;
+    if (grad && w->acc_block > 1 && !w->acc_part) return MMS_EINVAL;
+    const int64_t bytes = grid_elems(&w->g) * (int64_t)sizeof(float);
+    // every step's buffers first, so that a bad entry changes nothing
+    for (int n = n_hi; n >= n_lo; --n) {
+        const int i = n - n_lo;   // mus[i] = mu^n, mus[i+1] = mu^{n+1}, mus[i+2] = mu^{n+2}
+        const float *m2 = mus[i + 2], *m1 = mus[i + 1];
+        float *m0 = mus[i];
+        if (!m2 || !m0 || (n >= 1 && !m1)) return MMS_EINVAL;
+        const float *un = (grad && n >= 1) ? us[i] : nullptr;
+        if (grad && n >= 1 && !un) return MMS_EINVAL;
+        if (m1 && n >= 1 && overlap(m1, bytes, m0, bytes)) return MMS_EINVAL;
+        if (m2 != m0 && overlap(m2, bytes, m0, bytes)) return MMS_EINVAL;
+        if (un && overlap(un, bytes, m0, bytes)) return MMS_EINVAL;
+    }
+    if (grid_empty(&w->g)) return MMS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    // the gradient is accumulated as sum mu^{n+1} S(u^n) and divided by c2 once: the
+    // caller's grad is brought to that scale first and back at the end
+    if (grad)
+        if (int rc = wave_grad_c2(w, grad, +1, s)) return rc;
+    for (int n = n_hi; n >= n_lo; --n) {
+        const int i = n - n_lo;
+        const float *un = (grad && n >= 1) ? us[i] : nullptr;
+        int rc = wave_adjoint_mu_step(w, n, mus[i + 2], mus[i + 1], mus[i], resid, un,
+                                      n >= 1 ? grad : nullptr, s);
+        if (rc) return rc;
+    }
+    if (grad) return wave_grad_c2(w, grad, -1, s);
+    return MMS_OK;
+}
+
+int mms_wave_scale_mu(const mms_wave *w, const float *in, float *out, int dir, void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!in || !out || (dir != 1 && dir != -1)) return MMS_EINVAL;
+    const int64_t bytes = grid_elems(&w->g) * (int64_t)sizeof(float);
+    if (in != out && overlap(in, bytes, out, bytes)) return MMS_EINVAL;
+    if (grid_empty(&w->g)) return MMS_OK;
+    return wave_scale_mu(w, in, out, dir, (hipStream_t)stream);
 }
 
 int mms_wave_energy(const mms_wave *w, const float *u_n, const float *u_np1, double *out_dev,

@@ -23,7 +23,10 @@
 namespace mms {
 namespace {
 
-enum { MODE_FWD = 0, MODE_ADJ = 1, MODE_ENERGY = 2, MODE_GRAD = 3 };
+// ADJMU: the adjoint step carried in mu = C2 G lam, which has the forward step's form
+//   mu^n = G (2 mu^{n+1} - G mu^{n+2} + C2 S(mu^{n+1})) + C2 G R^T r^n
+// (one stencil stream, where the lam form forms C2 G lam from two)
+enum { MODE_FWD = 0, MODE_ADJ = 1, MODE_ENERGY = 2, MODE_GRAD = 3, MODE_ADJMU = 4 };
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
@@ -48,6 +51,7 @@ struct WaveArgs {
     int sponge_w;
     float sponge_a;
     int faces;
+    int mu_form;          // GRAD, first adjoint step: the adjoint variable is mu = C2 G lam
 };
 
 template <int R, int MODE, int TX, int TY>
@@ -243,18 +247,28 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                 const float p1v[4] = {pw1.x, pw1.y, pw1.z, pw1.w};
                 const float cv[4] = {ctr.x, ctr.y, ctr.z, ctr.w};
                 float r[4] = {0.f, 0.f, 0.f, 0.f};
-                if constexpr (MODE == MODE_FWD) {
-                    // p0 = u^{n-1}, p1 = C2, ctr = u^n
+                if constexpr (MODE == MODE_FWD || MODE == MODE_ADJMU) {
+                    // FWD: p0 = u^{n-1}, p1 = C2, ctr = u^n; ADJMU: p0 = mu^{n+2}, ctr = mu^{n+1}
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
                         const float G = gz * gown[e];
                         r[e] = G * (2.0f * cv[e] - G * p0v[e] + a.c2s * p1v[e] * o[e]);
                     }
-                    if (srcv != 0.f && z == a.src_z && y == a.src_y && a.src_x >= x0 &&
-                        a.src_x < x0 + 4) {
+                    if constexpr (MODE == MODE_FWD) {
+                        if (srcv != 0.f && z == a.src_z && y == a.src_y && a.src_x >= x0 &&
+                            a.src_x < x0 + 4) {
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            if (x0 + e == a.src_x) r[e] += srcv;
+                            for (int e = 0; e < 4; ++e)
+                                if (x0 + e == a.src_x) r[e] += srcv;
+                        }
+                    } else {
+                        // receivers: + C2 G r^n on the plane z = 0
+                        if (a.resid && z == 0 && live) {
+                            const float *rs = a.resid + (int64_t)y * g.nx + x0;
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                if (x0 + e < g.nx) r[e] += a.c2s * p1v[e] * (gz * gown[e]) * rs[e];
+                        }
                     }
                 } else if constexpr (MODE == MODE_ADJ) {
                     // p0 = lam^{n+2}, p1 = lam^{n+1}
@@ -302,7 +316,9 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                         float t[4];
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
-                            t[e] = MODE == MODE_FWD ? r[e] * r[e] : a.c2s * gz * gown[e] * p0v[e] * o[e];
+                            t[e] = MODE == MODE_FWD ? r[e] * r[e]
+                                   : a.mu_form ? p0v[e] * o[e]      // mu^{n+1} S(u^n), / c2 later
+                                               : a.c2s * gz * gown[e] * p0v[e] * o[e];
                         auto t64 = [&](int e) -> double {
                             return MODE == MODE_FWD ? (double)r[e] * (double)r[e] : (double)t[e];
                         };
@@ -404,8 +420,42 @@ __global__ void adjoint_first_kernel(WaveArgs a) {
                     gaxis(y, g.ny, W, a.sponge_a, a.faces & 4, a.faces & 8) *
                     gaxis(x, g.nx, W, a.sponge_a, a.faces & 1, a.faces & 2);
     float v = -G * G * a.p0[off];
-    if (a.resid && z == 0) v += a.resid[(int64_t)y * g.nx + x];
+    if (a.resid && z == 0) {
+        const float r = a.resid[(int64_t)y * g.nx + x];
+        v += a.mu_form ? a.c2s * a.c2[off] * G * r : r;   // mu form: C2 G R^T r^0
+    }
     a.out[off] = v;
+}
+
+// mu = C2 G lam (dir > 0) or lam = mu / (C2 G) (dir < 0) on the interior; in may equal out
+__global__ void scale_mu_kernel(WaveArgs a, const float *in, float *out, int dir) {
+    const Geom &g = a.g;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t np = (int64_t)g.nx * g.ny * g.nz;
+    if (i >= np) return;
+    const int x = (int)(i % g.nx);
+    const int y = (int)((i / g.nx) % g.ny);
+    const int z = (int)(i / ((int64_t)g.nx * g.ny));
+    const int64_t off = (int64_t)z * g.sz + (int64_t)y * g.sy + x;
+    const int W = a.sponge_w;
+    const float G = gaxis(z, g.nz, W, a.sponge_a, a.faces & 16, a.faces & 32) *
+                    gaxis(y, g.ny, W, a.sponge_a, a.faces & 4, a.faces & 8) *
+                    gaxis(x, g.nx, W, a.sponge_a, a.faces & 1, a.faces & 2);
+    const float f = a.c2s * a.c2[off] * G;
+    out[off] = dir > 0 ? in[off] * f : in[off] / f;
+}
+
+// dense FP64 grad times (dir > 0) or over (dir < 0) the c2 field
+__global__ void grad_c2_kernel(WaveArgs a, double *grad, int dir) {
+    const Geom &g = a.g;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t np = (int64_t)g.nx * g.ny * g.nz;
+    if (i >= np) return;
+    const int x = (int)(i % g.nx);
+    const int y = (int)((i / g.nx) % g.ny);
+    const int z = (int)(i / ((int64_t)g.nx * g.ny));
+    const double c = (double)a.c2[(int64_t)z * g.sz + (int64_t)y * g.sy + x];
+    grad[i] = dir > 0 ? grad[i] * c : grad[i] / c;
 }
 
 __global__ void dense_to_grid_kernel(const double *in, float *out, int nx, int ny, int64_t sy,
@@ -538,6 +588,57 @@ int wave_adjoint_step(const mms_wave *w, int n, const float *l2, const float *l1
         b.part_last = ph == K - 1 || n == 1;
     }
     return launch_mode<MODE_GRAD>(b, &w->g, w->radius, s);
+}
+
+int wave_adjoint_mu_step(const mms_wave *w, int n, const float *m2, const float *m1, float *m0,
+                         const float *resid, const float *un, double *grad, hipStream_t s) {
+    WaveArgs a = base_args(w);
+    const int64_t o = (int64_t)w->g.halo * (w->g.sz + w->g.sy + 1);
+    a.p0 = m2 + o;
+    a.out = m0 + o;
+    a.resid = resid ? resid + (int64_t)n * w->g.ny * w->g.nx : nullptr;
+    a.mu_form = 1;
+    if (n == 0) {
+        fill_geom(a.g, &w->g);
+        const int64_t np = w->g.nx * w->g.ny * w->g.nz;
+        hipLaunchKernelGGL(adjoint_first_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, a);
+        return check_launch("adjoint_first_kernel");
+    }
+    a.f0 = m1 + o;
+    const int rc = launch_mode<MODE_ADJMU>(a, &w->g, w->radius, s);
+    if (rc || !grad) return rc;
+    // gradient terms mu^{n+1} S(u^n) (the division by c2 happens once per call)
+    WaveArgs b = base_args(w);
+    b.f0 = un + o;
+    b.p0 = m1 + o;
+    b.acc64 = grad;
+    b.mu_form = 1;
+    if (w->acc_block > 1) {
+        const int K = w->acc_block, ph = (w->nt - 1 - n) % K;
+        b.part = w->acc_part;
+        b.part_first = ph == 0;
+        b.part_last = ph == K - 1 || n == 1;
+    }
+    return launch_mode<MODE_GRAD>(b, &w->g, w->radius, s);
+}
+
+int wave_scale_mu(const mms_wave *w, const float *in, float *out, int dir, hipStream_t s) {
+    WaveArgs a = base_args(w);
+    fill_geom(a.g, &w->g);
+    const int64_t o = (int64_t)w->g.halo * (w->g.sz + w->g.sy + 1);
+    const int64_t np = w->g.nx * w->g.ny * w->g.nz;
+    hipLaunchKernelGGL(scale_mu_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, a,
+                       in + o, out + o, dir);
+    return check_launch("scale_mu_kernel");
+}
+
+int wave_grad_c2(const mms_wave *w, double *grad, int dir, hipStream_t s) {
+    WaveArgs a = base_args(w);
+    fill_geom(a.g, &w->g);
+    const int64_t np = w->g.nx * w->g.ny * w->g.nz;
+    hipLaunchKernelGGL(grad_c2_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, a, grad,
+                       dir);
+    return check_launch("grad_c2_kernel");
 }
 
 int wave_record(const mms_wave *w, int n, const float *u, hipStream_t s) {

@@ -115,6 +115,23 @@ def test_wave_validation(L):
     arr = (vp * 3)(a, b, c)
     assert L.mms_wave_forward(ctypes.byref(w), 0, 3, arr, None) == -1
     assert L.mms_wave_forward(ctypes.byref(w), 1, 11, arr, None) == -1
+    # mu-form adjoint: range, missing entries, aliasing, workspace and direction checks
+    mus = (vp * 5)(a, b, c, a, b)
+    us = (vp * 5)(c, c, c, c, c)
+    assert L.mms_wave_adjoint_mu(ctypes.byref(w), 10, 0, mus, None, None, None, None) == -1
+    assert L.mms_wave_adjoint_mu(ctypes.byref(w), 2, 3, mus, None, None, None, None) == -1
+    assert L.mms_wave_adjoint_mu(ctypes.byref(w), 2, 0, None, None, None, None, None) == -1
+    assert L.mms_wave_adjoint_mu(ctypes.byref(w), 2, 0, mus, None, None, vp(0x40), None) == -1
+    bad = (vp * 5)(b, c, a, a, c)                           # at n = 2, mu^n aliases mu^{n+1}
+    assert L.mms_wave_adjoint_mu(ctypes.byref(w), 2, 0, bad, None, None, None, None) == -1
+    hole = (vp * 5)(a, b, None, a, b)
+    assert L.mms_wave_adjoint_mu(ctypes.byref(w), 2, 0, hole, None, None, None, None) == -1
+    w.acc_block = 8                                                       # blocks need acc_part
+    assert L.mms_wave_adjoint_mu(ctypes.byref(w), 2, 0, mus, us, None, vp(0x40), None) == -1
+    w.acc_block = 0
+    assert L.mms_wave_scale_mu(ctypes.byref(w), a, b, 0, None) == -1
+    assert L.mms_wave_scale_mu(ctypes.byref(w), a, vp(0x100040), 1, None) == -1  # partial overlap
+    assert L.mms_wave_scale_mu(ctypes.byref(w), None, b, 1, None) == -1
 
 
 def test_python_binding_requires_library(monkeypatch, tmp_path):

@@ -246,10 +246,15 @@ def autograd_problem(mms, n, nt, seed, K, W=8):
     return s, grid, m, prob
 
 
-def test_checkpointing_gives_identical_gradient(mms):
+@pytest.mark.parametrize("form", ["lam", "mu"])
+def test_checkpointing_gives_identical_gradient(mms, form):
+    """Segment length changes only where the forward levels come from: the lam-form gradient
+    is bit-identical; the mu form scales the FP64 sum by c2 and back once per segment, so its
+    FP64 sums may differ in the last bits, which FP32 output hides or shows as one ulp."""
     from paper_2507_11067_amd.autograd import misfit, propagate
     n, nt = 32, 120
     s, grid, m, prob = autograd_problem(mms, n, nt, 40, K=50)
+    prob.adjoint_form = form
     d_obs = torch.zeros((nt, n, n), device=DEV)
     grads = []
     for K in (50, 7, 1000):
@@ -262,8 +267,36 @@ def test_checkpointing_gives_identical_gradient(mms):
         grads.append((mt.grad.clone(), z0.grad.clone(), z1.grad.clone()))
     for gk in grads[1:]:
         for a, b in zip(grads[0], gk):
-            assert torch.equal(a, b)
+            if form == "lam":
+                assert torch.equal(a, b)
+            else:
+                ulp = torch.finfo(torch.float32).eps * a.abs().max()
+                assert (a - b).abs().max() <= ulp
     assert torch.count_nonzero(grads[0][0]) > 0
+    assert prob.stats["adjoint_form"] == form
+
+
+def test_gradient_mu_form_matches_lambda_form(mms):
+    """dJ/dm, dJ/du0 and dJ/du1 through the mu-form adjoint against the lam form (m > 0,
+    checkpoints every 13 steps, gradient blocks of 8)."""
+    from paper_2507_11067_amd.autograd import misfit, propagate
+    n, nt = 40, 150
+    s, grid, m, prob = autograd_problem(mms, n, nt, 43, K=13)
+    d_obs = torch.zeros((nt, n, n), device=DEV)
+    u0, u1 = T(smooth(44, grid)), T(smooth(45, grid))
+    out = []
+    for form in ("lam", "mu"):
+        prob.adjoint_form = form
+        mt = T(m).requires_grad_(True)
+        z0 = u0.clone().requires_grad_(True)
+        z1 = u1.clone().requires_grad_(True)
+        J = misfit(propagate(mt, z0, z1, prob), d_obs)
+        J.backward()
+        out.append([interior(t.grad.cpu().numpy(), grid) for t in (mt, z0, z1)])
+    errs = [rel_errors(b, a)[0] for a, b in zip(out[0], out[1])]
+    print("mu vs lam form, dJ/dm dJ/du0 dJ/du1: " + " ".join(f"{e:.2e}" for e in errs))
+    assert all(np.abs(a).max() > 0 for a in out[0])
+    assert max(errs) <= 1e-5, errs
 
 
 def test_blocked_gradient_matches_per_step(mms):
@@ -344,3 +377,86 @@ def test_blocked_accumulation_wide_rows(mms, nx):
     print(f"nx {nx}: blocked vs per-step image {ri:.2e}, gradient {rg:.2e}")
     assert np.abs(images[0]).max() > 0 and np.abs(grads[0]).max() > 0
     assert ri <= 1e-6 and rg <= 1e-6
+
+
+def mu_problem(mms, nx, ny, nz, nt, seed):
+    grid, c2, f, src, _ = setup_small(mms, nx, nt, seed, W=8, ny=ny, nz=nz)
+    w = gpu_wave(mms, grid, T(c2), T(f), src, nt, 8, alpha=0.05)
+    lam_top = [T(smooth(seed + 1, grid)), T(smooth(seed + 2, grid))]
+    us = [T(smooth(seed + 10 + i, grid)) for i in range(nt)]
+    resid = T(np.random.default_rng(seed + 3).standard_normal((nt, ny, nx)))
+    return grid, w, lam_top, us, resid
+
+
+@pytest.mark.parametrize("dims,block", [((40, 36, 30), 1), ((40, 36, 30), 8), ((300, 9, 13), 4)],
+                         ids=["40x36x30-k1", "40x36x30-k8", "300x9x13-k4"])
+def test_adjoint_mu_form_matches_lambda_form(mms, dims, block):
+    """The adjoint carried in mu = C2 G lam (forward-step form) against the lam form: every
+    level after conversion back, and the gradient (per step and in blocks)."""
+    nx, ny, nz = dims
+    nt = 40
+    grid, w, lam_top, us, resid = mu_problem(mms, nx, ny, nz, nt, 60)
+    grads, lows = [], []
+    for form in ("lam", "mu"):
+        part = torch.full((nz, ny, nx), 5.0, device=DEV)
+        w.set_accumulation(part if block > 1 else None, block)
+        grad = torch.full((nz, ny, nx), 0.5, dtype=torch.float64, device=DEV)
+        bufs = [grid.zeros(DEV) for _ in range(nt + 2)]
+        if form == "lam":
+            bufs[nt].copy_(lam_top[0])
+            bufs[nt + 1].copy_(lam_top[1])
+            w.adjoint(nt - 1, 0, bufs, us=us, resid=resid, grad=grad)
+        else:
+            w.scale_mu(lam_top[0], bufs[nt], +1)
+            w.scale_mu(lam_top[1], bufs[nt + 1], +1)
+            w.adjoint_mu(nt - 1, 0, bufs, us=us, resid=resid, grad=grad)
+            for b in bufs[:nt]:
+                w.scale_mu(b, b, -1)
+        torch.cuda.synchronize()
+        grads.append(grad.cpu().numpy() - 0.5)
+        lows.append([interior(b.cpu().numpy(), grid) for b in bufs[:3]])
+    rg, _ = rel_errors(grads[1], grads[0])
+    rl = max(rel_errors(b, a)[0] for a, b in zip(lows[0], lows[1]))
+    print(f"{dims} K={block}: mu vs lam form: levels 0-2 {rl:.2e}, gradient {rg:.2e}")
+    assert np.abs(grads[0]).max() > 0
+    assert rl <= 1e-5 and rg <= 1e-5, (rl, rg)
+
+
+def test_scale_mu_round_trip(mms):
+    grid, w, lam_top, _, _ = mu_problem(mms, 37, 19, 11, 4, 70)
+    x = lam_top[0]
+    mu = grid.zeros(DEV)
+    w.scale_mu(x, mu, +1)
+    back = T(np.full(grid.shape, 9.0))
+    w.scale_mu(mu, back, -1)
+    torch.cuda.synchronize()
+    r, _ = rel_errors(interior(back.cpu().numpy(), grid), interior(x.cpu().numpy(), grid))
+    assert r <= 1e-6
+    halo = back.cpu().numpy().copy()
+    interior(halo, grid)[...] = 9.0
+    assert np.all(halo == 9.0)          # halo cells untouched
+
+
+def test_dot_product_identity_mu_form(mms):
+    """<A x, y> = <x, A^T y> with A^T applied through the mu form."""
+    n, nt, seed, W = 64, 400, 30, 8
+    grid, c2, f, src, _ = setup_small(mms, n, nt, seed, W=W)
+    traces = torch.zeros((nt, n, n), device=DEV)
+    w = gpu_wave(mms, grid, T(c2), None, src, nt, W, traces=traces)
+    u0, u1 = T(smooth(seed + 1, grid)), T(smooth(seed + 2, grid))
+    bufs = [u0.clone(), u1.clone(), grid.zeros(DEV)]
+    w.record(0, bufs[0])
+    w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+    from scipy.ndimage import gaussian_filter
+    yn = gaussian_filter(np.random.default_rng(seed + 3).standard_normal((nt, n, n)), sigma=2.0)
+    y = torch.from_numpy((yn / np.abs(yn).max()).astype(np.float32)).to(DEV)
+    mu = [grid.zeros(DEV) for _ in range(3)]
+    w.adjoint_mu(nt - 1, 0, [mu[i % 3] for i in range(nt + 2)], resid=y)
+    lam0, lam1 = grid.zeros(DEV), grid.zeros(DEV)
+    w.scale_mu(mu[0], lam0, -1)
+    w.scale_mu(mu[1], lam1, -1)
+    lhs = mms.flat_dot(traces, y)
+    rhs = mms.dot(u0, lam0, grid) + mms.dot(u1, lam1, grid)
+    rel = abs(lhs - rhs) / abs(lhs)
+    print(f"dot test (mu form) 64^3 x 400: rel {rel:.2e}")
+    assert rel <= 1e-5
