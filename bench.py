@@ -146,10 +146,14 @@ def main():
     skip = set(s for s in args.skip.split(",") if s)
     dev = torch.device("cuda:0")
     n = args.n
-    grid = mms.Grid(n, n, n)
+    # rows padded to a multiple of 32 elements and placed so that every interior row
+    # starts on a 128-byte boundary (mms_grid_aligned): the output rows of the sweeps
+    # cover whole cache lines (measured: star r4 653 -> 717 Gpoints/s at 512^3)
+    grid = mms.Grid.aligned(n, n, n)
     log(f"[bench] generating {n}^3 input (seed 2)")
     x_np = synth.uniform_grid(2, n, n, n, sy=grid.sy)
-    x = torch.from_numpy(x_np).to(dev)
+    x = grid.zeros(dev)
+    x.copy_(torch.from_numpy(x_np))
     outs = {k: grid.zeros(dev) for k in ("star", "box2", "box4")}
     c_star = synth.star_coeffs_laplacian(4)
     c_box2 = synth.box_coeffs(3, 2)
@@ -238,7 +242,12 @@ def main():
 
     # context for the HBM-bound rows: what a plain device copy of the same padded grid
     # moves on this GPU (read + write), timed the same way
-    cms = time_launches(torch, lambda: outs["box2"].copy_(x))
+    # (two fresh flat buffers of the grid's size, so that torch's copy sees its usual
+    # allocator alignment)
+    ca = x.reshape(-1).clone()
+    cb = torch.empty_like(ca)
+    cms = time_launches(torch, lambda: cb.copy_(ca))
+    del ca, cb
     copy_gbs = 2.0 * x.numel() * 4 / (cms * 1e-3) / 1e9
     rooflines["star"]["copy_gbs"] = copy_gbs
     rooflines["star"]["frac_of_copy"] = kernels["star"]["gbs"] / copy_gbs
@@ -255,7 +264,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n}^3 FP32 sweeps, one step = radius-4 star + radius-2 box + "
                                "radius-4 box (4-cell zero halo, uniform [-1,1] seed 2)",
-                   "grid": [n, n, n], "halo": 4, "points_per_step": 3 * pts},
+                   "grid": [n, n, n], "halo": 4, "row_pitch": grid.sy,
+                   "interior_rows_128B_aligned": True, "points_per_step": 3 * pts},
         "roofline": roof,
         "rooflines": rooflines,
         "kernels": kernels,
@@ -522,6 +532,12 @@ def bench_gradient(torch, mms, synth, dev, n=256, nt=1000, K=50):
     z = grid.zeros(dev)
     with torch.no_grad():
         d_obs = propagate(mgrid(s0.v), z, z, prob)
+    # one untimed pass first, so that the timed pass reuses the caching allocator's blocks:
+    # the first pass's device allocations (about 7 GB of checkpoints and segment levels)
+    # and their first-touch mapping cost 40-110 ms and are not part of a step
+    mw = mgrid(s.v).requires_grad_(True)
+    misfit(propagate(mw, z, z, prob), d_obs).backward()
+    del mw
     m = mgrid(s.v).requires_grad_(True)
     torch.cuda.synchronize()
     a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
@@ -831,7 +847,8 @@ def collect_counters(args):
                                        "source_sha": source_sha(COUNTED[name][0])}
     # 2. counters per kernel, copy first (calibration)
     n = 512
-    grid_bytes = (n + 8) * (n + 8) * (n + 8) * 4        # the padded 520^3 FP32 grid
+    sy = ((n + 8 + 31) // 32) * 32                      # the headline layout (Grid.aligned)
+    grid_bytes = (n + 8) * (n + 8) * sy * 4             # one padded FP32 grid
     factors = {}
     for name, (src, sym, bpp) in COUNTED.items():
         e = {"source": src, "source_sha": source_sha(src), "symbol": sym}
@@ -881,7 +898,7 @@ def collect_counters(args):
                      f"{(v['avg_ns'] or 0) / 1e3:9.2f} us   command: {v['command']}")
     lines.append("")
     lines.append("## HBM counters (per dispatch; KiB as read, bytes after copy calibration)")
-    lines.append(f"calibration: plain copy of one {n + 8}^3 FP32 grid ({grid_bytes} B each way): "
+    lines.append(f"calibration: plain copy of one {n + 8}x{n + 8}x{sy} FP32 grid ({grid_bytes} B each way): "
                  f"FETCH factor {factors['FETCH_SIZE']:.4f}, WRITE factor "
                  f"{factors['WRITE_SIZE']:.4f}")
     for name, e in summary["kernels"].items():
@@ -917,7 +934,9 @@ def profile_only(args, torch, mms, synth, grid, x, outs, sweeps, c_box4, c_box3,
         c = c_box4 if r == 4 else c_box3
         f = lambda: mms.stencil_apply(x, out, grid, "box", r, c, precision=prec)
     elif k == "copy":
-        f = lambda: out.copy_(x)
+        ca = x.reshape(-1).clone()      # flat buffers of the grid's size, allocator-aligned
+        cb = torch.empty_like(ca)
+        f = lambda: cb.copy_(ca)
     elif k in table1_kernels(synth):
         shape, r, c, _ = table1_kernels(synth)[k]
         f = lambda: mms.stencil_apply(x, out, grid, shape, r, c)

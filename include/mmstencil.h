@@ -280,6 +280,22 @@ int mms_flat_misfit_f64(const float *a, const float *b, float *resid, int64_t n,
  */
 int mms_dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, void *stream);
 
+/*
+ * mms_grid_aligned -- host helper: fill *g with the layout whose interior rows
+ * start on 128-byte boundaries, and return in *lead the number of elements to
+ * place in front of the array.  sy = roundup(roundup4(nx) + 2H, 32),
+ * sz = sy (ny + 2H), lead = (32 - H % 32) % 32.  An array that starts lead
+ * elements after a 128-byte aligned address (device allocators return at least
+ * that) has interior point (z, y, 0) on a 128-byte boundary for every z, y, so
+ * a sweep's output rows cover whole cache lines whenever 4 nx is a multiple of
+ * 128 (no partial-line writes).  Allocate lead + (nz + 2H) sz elements.  Any
+ * other layout that meets the mms_grid requirements stays valid; this one is
+ * faster for the memory-bound sweeps.  Returns MMS_EINVAL for a null output,
+ * negative extents, or a halo that is not a positive multiple of 4.
+ */
+int mms_grid_aligned(int64_t nx, int64_t ny, int64_t nz, int32_t halo, mms_grid *g,
+                     int64_t *lead);
+
 /* Tuning of the sweep launches: z-chunk length per shape and precision (0 = automatic). */
 int mms_set_zchunk(int shape, int precision, int zchunk);
 

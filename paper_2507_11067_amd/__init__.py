@@ -40,6 +40,19 @@ class Grid:
             need = ((self.nx + 3) // 4) * 4 + 2 * self.halo
             object.__setattr__(self, "sy", ((need + 3) // 4) * 4)
 
+    @classmethod
+    def aligned(cls, nx: int, ny: int, nz: int, halo: int = 4) -> "Grid":
+        """The layout of mms_grid_aligned: rows padded to 32 elements, so that with
+        zeros()'s placement every interior row starts on a 128-byte boundary."""
+        need = ((nx + 3) // 4) * 4 + 2 * halo
+        return cls(nx, ny, nz, halo, ((need + 31) // 32) * 32)
+
+    @property
+    def lead(self) -> int:
+        """Elements zeros() places in front of an FP32 array: (32 - H % 32) % 32 when
+        sy is a multiple of 32 (interior rows then start on 128-byte boundaries), else 0."""
+        return (32 - self.halo % 32) % 32 if self.sy % 32 == 0 else 0
+
     @property
     def shape(self):
         return (self.nz + 2 * self.halo, self.ny + 2 * self.halo, self.sy)
@@ -56,7 +69,11 @@ class Grid:
         return _lib.MmsGrid(self.nx, self.ny, self.nz, self.halo, 0, self.sy, self.sz)
 
     def zeros(self, device="cuda", dtype=torch.float32) -> torch.Tensor:
-        return torch.zeros(self.shape, device=device, dtype=dtype)
+        lead = self.lead if dtype == torch.float32 else 0
+        if lead == 0:
+            return torch.zeros(self.shape, device=device, dtype=dtype)
+        n = self.shape[0] * self.shape[1] * self.shape[2]
+        return torch.zeros(lead + n, device=device, dtype=dtype)[lead:].view(self.shape)
 
     def interior(self, t: torch.Tensor) -> torch.Tensor:
         H = self.halo

@@ -13,7 +13,7 @@ MMS_FP32, MMS_BF16X3, MMS_FP16X3S, MMS_BF16X1 = 0, 1, 2, 3
 EXPORTS = ("mms_stencil_apply", "mms_wave_step", "mms_wave_record", "mms_wave_forward",
            "mms_wave_adjoint_step", "mms_wave_adjoint", "mms_wave_adjoint_mu", "mms_wave_scale_mu",
            "mms_wave_energy", "mms_dot_f64",
-           "mms_flat_dot_f64", "mms_flat_misfit_f64", "mms_dense_to_grid", "mms_set_zchunk",
+           "mms_flat_dot_f64", "mms_flat_misfit_f64", "mms_dense_to_grid", "mms_grid_aligned", "mms_set_zchunk",
            "mms_strerror", "mms_last_error", "mms_abi_version", "mms_vti_step", "mms_tti_step")
 
 
@@ -70,6 +70,7 @@ def lib():
         L.mms_wave_adjoint_mu.argtypes = [wp, i32, i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                           vp, vp, vp]
         L.mms_wave_scale_mu.argtypes = [wp, vp, vp, i32, vp]
+        L.mms_grid_aligned.argtypes = [i64, i64, i64, ctypes.c_int32, gp, ctypes.POINTER(i64)]
         L.mms_wave_energy.argtypes = [wp, vp, vp, vp, vp]
         L.mms_vti_step.argtypes = [wp, i32] + [vp] * 8 + [vp]
         L.mms_tti_step.argtypes = [wp, ctypes.POINTER(MmsTti), i32] + [vp] * 6 + [vp]

@@ -117,6 +117,22 @@ const char *mms_strerror(int code) {
 
 const char *mms_last_error(void) { return g_last; }
 
+int mms_grid_aligned(int64_t nx, int64_t ny, int64_t nz, int32_t halo, mms_grid *g,
+                     int64_t *lead) {
+    if (!g || !lead || nx < 0 || ny < 0 || nz < 0 || halo < 4 || halo % 4 != 0) return MMS_EINVAL;
+    if (nx > (1 << 30) || ny > (1 << 30) || nz > (1 << 30)) return MMS_EINVAL;
+    const int64_t need = ((nx + 3) & ~(int64_t)3) + 2 * (int64_t)halo;
+    g->nx = nx;
+    g->ny = ny;
+    g->nz = nz;
+    g->halo = halo;
+    g->pad_ = 0;
+    g->sy = (need + 31) & ~(int64_t)31;
+    g->sz = g->sy * (ny + 2 * (int64_t)halo);
+    *lead = (32 - halo % 32) % 32;
+    return MMS_OK;
+}
+
 int mms_set_zchunk(int shape, int precision, int zchunk) {
     if (shape < 0 || shape > 3 || precision < 0 || precision > 3 || zchunk < 0) return MMS_EINVAL;
     g_zchunk[shape][precision] = zchunk;

@@ -141,3 +141,32 @@ def test_python_binding_requires_library(monkeypatch, tmp_path):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_grid_aligned_layout(L):
+    """mms_grid_aligned against Grid.aligned, and zeros()'s placement: interior rows on
+    128-byte (32-element) boundaries relative to the allocation."""
+    import ctypes
+    import torch
+    from paper_2507_11067_amd import Grid, _lib
+    for nx, ny, nz, H in [(512, 512, 512, 4), (400, 3, 2, 4), (1, 1, 1, 8), (0, 5, 5, 4),
+                          (256, 7, 9, 32), (29, 2, 3, 12)]:
+        g = _lib.MmsGrid()
+        lead = ctypes.c_int64(-1)
+        assert L.mms_grid_aligned(nx, ny, nz, H, ctypes.byref(g), ctypes.byref(lead)) == 0
+        p = Grid.aligned(nx, ny, nz, H)
+        assert (g.nx, g.ny, g.nz, g.halo, g.sy, g.sz) == (nx, ny, nz, H, p.sy, p.sz)
+        assert lead.value == p.lead
+        assert g.sy % 32 == 0 and g.sy >= ((nx + 3) // 4) * 4 + 2 * H and g.sy - 32 < ((nx + 3) // 4) * 4 + 2 * H
+        t = p.zeros("cpu")
+        assert tuple(t.shape) == p.shape and t.is_contiguous() and t.storage_offset() == p.lead
+        assert (p.lead + H * (p.sz + p.sy + 1)) % 32 == 0
+        assert not t.any()
+    # the default layout keeps its pitch and no lead
+    d = Grid(512, 512, 512)
+    assert d.sy == 520 and d.lead == 0 and d.zeros("cpu").storage_offset() == 0
+    g = _lib.MmsGrid()
+    lead = ctypes.c_int64()
+    for args in [(-1, 1, 1, 4), (1, 1, 1, 2), (1, 1, 1, 0), (1, -1, 1, 4)]:
+        assert L.mms_grid_aligned(*args, ctypes.byref(g), ctypes.byref(lead)) == -1
+    assert L.mms_grid_aligned(1, 1, 1, 4, None, ctypes.byref(lead)) == -1

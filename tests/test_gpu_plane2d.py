@@ -23,8 +23,10 @@ def mms():
 
 
 def run(mms, x_np, grid, shape, r, c, out_fill=0.0):
-    x = torch.from_numpy(x_np).to(DEV)
-    out = torch.full(grid.shape, out_fill, dtype=torch.float32, device=DEV)
+    # grid.zeros() places the arrays (interior rows on 128-byte boundaries for Grid.aligned)
+    x = grid.zeros(DEV)
+    x.copy_(torch.from_numpy(x_np))
+    out = grid.zeros(DEV).fill_(out_fill)
     mms.stencil_apply(x, out, grid, shape, r, c)
     torch.cuda.synchronize()
     return out.cpu().numpy()
@@ -90,7 +92,8 @@ def test_plane2d_empty_and_deterministic(mms):
 @pytest.fixture(scope="module")
 def big512():
     n = 512
-    x = synth.uniform_grid(2, n, n, n)
+    # the benchmark's layout: rows padded to 544, interior rows on 128-byte boundaries
+    x = synth.uniform_grid(2, n, n, n, sy=((n + 8 + 31) // 32) * 32)
     return n, x, x.astype(np.float64)
 
 
@@ -101,7 +104,7 @@ TABLE1_2D = [("star2d", 2), ("star2d", 4), ("box2d", 2), ("box2d", 3)]
 def test_table1_2d_512_sampled(mms, big512, shape, r):
     """Table I 2-D kernels on the 512^3 stack in the benchmark's launch shape."""
     n, x, x64 = big512
-    grid = mms.Grid(n, n, n)
+    grid = mms.Grid.aligned(n, n, n)
     c = synth.star2d_coeffs_laplacian(r) if shape == "star2d" else synth.box2d_coeffs(10 + r, r)
     got = run(mms, x, grid, shape, r, c)
     rng = np.random.default_rng(20 + r)

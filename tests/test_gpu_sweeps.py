@@ -25,8 +25,10 @@ def mms():
 
 
 def run(mms, x_np, grid, shape, r, c, prec="fp32", out_fill=0.0):
-    x = torch.from_numpy(x_np).to(DEV)
-    out = torch.full(grid.shape, out_fill, dtype=torch.float32, device=DEV)
+    # grid.zeros() places the arrays (interior rows on 128-byte boundaries for Grid.aligned)
+    x = grid.zeros(DEV)
+    x.copy_(torch.from_numpy(x_np))
+    out = grid.zeros(DEV).fill_(out_fill)
     mms.stencil_apply(x, out, grid, shape, r, c, precision=prec)
     torch.cuda.synchronize()
     return out.cpu().numpy()
@@ -182,14 +184,15 @@ def sample_points(rng, n, count=4000):
 @pytest.fixture(scope="module")
 def big512():
     n = 512
-    x = synth.uniform_grid(2, n, n, n)
+    # the benchmark's layout: rows padded to 544, interior rows on 128-byte boundaries
+    x = synth.uniform_grid(2, n, n, n, sy=((n + 8 + 31) // 32) * 32)
     return n, x, x.astype(np.float64)
 
 
 def test_star_512_sampled(mms, big512):
     """Full-size workload (512^3, radius-4 Laplacian) in the benchmark's launch shape."""
     n, x, x64 = big512
-    grid = mms.Grid(n, n, n)
+    grid = mms.Grid.aligned(n, n, n)
     c = synth.star_coeffs_laplacian(4)
     got = run(mms, x, grid, "star", 4, c)
     pts = sample_points(np.random.default_rng(14), n)
@@ -205,7 +208,7 @@ def test_star_512_sampled(mms, big512):
                                     (4, "bf16x1")])
 def test_box_512_sampled(mms, big512, r, prec):
     n, x, x64 = big512
-    grid = mms.Grid(n, n, n)
+    grid = mms.Grid.aligned(n, n, n)
     c = synth.box_coeffs({2: 3, 3: 6, 4: 4}[r], r)
     got = run(mms, x, grid, "box", r, c, prec)
     pts = sample_points(np.random.default_rng(15 + r), n, 2000)
@@ -217,3 +220,40 @@ def test_box_512_sampled(mms, big512, r, prec):
         assert rmax < 2e-2
     else:
         assert rmax <= TOL, rmax
+
+
+@pytest.mark.parametrize("dims", [(64, 64, 64), (300, 9, 13), (133, 37, 20)],
+                         ids=lambda d: "x".join(map(str, d)))
+def test_aligned_layout_bit_identical(mms, dims):
+    """Sweeps on the 128-byte-row layout (Grid.aligned with zeros()'s placement) against the
+    default layout: the same kernels at other addresses, so the interiors are bit-identical
+    and the halo stays unwritten; the star is also checked against the oracle."""
+    nx, ny, nz = dims
+    ga, gd = mms.Grid.aligned(nx, ny, nz), mms.Grid(nx, ny, nz)
+    xa_np = synth.uniform_grid(7, nx, ny, nz, sy=ga.sy)
+    xa = ga.zeros(DEV)
+    xa.copy_(torch.from_numpy(xa_np))
+    assert (xa.data_ptr() + 4 * ga.halo * (ga.sz + ga.sy + 1)) % 128 == 0
+    xd = torch.from_numpy(synth.uniform_grid(7, nx, ny, nz, sy=gd.sy)).to(DEV)
+    rng = np.random.default_rng(8)
+    cases = [("star", 4, synth.star_coeffs_random(9, 4), "fp32"),
+             ("box", 1, synth.box_coeffs(10, 1), "fp32"),
+             ("box", 2, synth.box_coeffs(11, 2), "fp32"),
+             ("box", 4, synth.box_coeffs(12, 4), "bf16x3"),
+             ("star2d", 4, rng.uniform(-1, 1, (2, 9)).astype(np.float32), "fp32"),
+             ("box2d", 3, rng.uniform(-1, 1, (7, 7)).astype(np.float32), "fp32")]
+    for shape, r, c, prec in cases:
+        oa = ga.zeros(DEV).fill_(7.0)
+        od = torch.full(gd.shape, 7.0, device=DEV)
+        mms.stencil_apply(xa, oa, ga, shape, r, c, precision=prec)
+        mms.stencil_apply(xd, od, gd, shape, r, c, precision=prec)
+        torch.cuda.synchronize()
+        a, d = oa.cpu().numpy(), od.cpu().numpy()
+        assert np.array_equal(interior(a, ga), interior(d, gd)), (shape, r, prec)
+        h = a.copy()
+        interior(h, ga)[...] = 7.0
+        assert np.all(h == 7.0), (shape, r, prec)
+        if shape == "star":
+            ref = oracle.star(xa_np, nx, ny, nz, r, c)
+            rmax, _ = rel_errors(interior(a, ga), interior(ref, ga))
+            assert rmax <= TOL, rmax

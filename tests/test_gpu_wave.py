@@ -460,3 +460,40 @@ def test_dot_product_identity_mu_form(mms):
     rel = abs(lhs - rhs) / abs(lhs)
     print(f"dot test (mu form) 64^3 x 400: rel {rel:.2e}")
     assert rel <= 1e-5
+
+
+def test_aligned_layout_wave_bit_identical(mms):
+    """Forward steps, the lam- and mu-form adjoint with the gradient on the 128-byte-row
+    layout against the default layout: bit-identical fields and gradient."""
+    nx, ny, nz, nt = 300, 9, 13, 12
+    out = []
+    for grid in (mms.Grid(nx, ny, nz), mms.Grid.aligned(nx, ny, nz)):
+        _, c2, f, src, _ = setup_small(mms, nx, nt, 90, ny=ny, nz=nz)
+        c2g = synth.padded_zeros(nx, ny, nz, sy=grid.sy)
+        synth.interior(c2g, nx, ny, nz)[...] = synth.interior(c2, nx, ny, nz)
+        def dev(a):
+            t = grid.zeros(DEV)
+            t.copy_(torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)))
+            return t
+        w = gpu_wave(mms, grid, dev(c2g), T(f), src, nt, 4, traces=torch.zeros((nt, ny, nx), device=DEV))
+        bufs = [dev(synth.padded_zeros(nx, ny, nz, sy=grid.sy)) for _ in range(3)]
+        w.record(0, bufs[0])
+        w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
+        us = [dev(synth.padded_zeros(nx, ny, nz, sy=grid.sy)) for _ in range(nt)]
+        for i, u in enumerate(us):
+            grid.interior(u).copy_(torch.from_numpy(synth.interior(
+                synth.smooth_random_grid(100 + i, nx, ny, nz), nx, ny, nz)))
+        resid = T(np.random.default_rng(91).standard_normal((nt, ny, nx)))
+        res = [grid.interior(bufs[(nt - 1) % 3]).cpu().numpy(), w.traces.cpu().numpy()]
+        for form in ("lam", "mu"):
+            lam = [grid.zeros(DEV) for _ in range(3)]
+            grad = torch.zeros((nz, ny, nx), dtype=torch.float64, device=DEV)
+            adj = w.adjoint_mu if form == "mu" else w.adjoint
+            adj(nt - 1, 0, [lam[i % 3] for i in range(nt + 2)], us=us, resid=resid, grad=grad)
+            torch.cuda.synchronize()
+            res += [grid.interior(lam[0]).cpu().numpy(), grid.interior(lam[1]).cpu().numpy(),
+                    grad.cpu().numpy()]
+        out.append(res)
+    for a, b in zip(*out):
+        assert np.abs(a).max() > 0
+        assert np.array_equal(a, b)
