@@ -587,6 +587,31 @@ def bench_gradient(torch, mms, synth, dev, n=256, nt=1000, K=50):
     return res
 
 
+def gradient_pass(torch, mms, synth, dev, n=256, nt=1000, K=50):
+    """One forward + backward pass of the 256^3 x 1000 gradient workload, as a callable."""
+    from paper_2507_11067_amd.autograd import Problem, misfit, propagate
+    s = synth.wave_setup(n, nt, seed=8, sponge_width=32)
+    s0 = synth.wave_setup(n, nt, seed=None, sponge_width=32, dt=s.dt)
+    grid = mms.Grid(n, n, n)
+    prob = Problem(grid, tuple(LAP), nt, s.h, s.dt, s.src, torch.from_numpy(s.src_dt2f).to(dev),
+                   s.sponge_width, s.sponge_alpha, s.sponge_faces, checkpoint_every=K)
+
+    def mgrid(v):
+        m = synth.padded_zeros(n, n, n)
+        synth.interior(m, n, n, n)[...] = (v ** 2).astype(np.float32)
+        return torch.from_numpy(m).to(dev)
+
+    z = grid.zeros(dev)
+    with torch.no_grad():
+        d_obs = propagate(mgrid(s0.v), z, z, prob)
+    m_val = mgrid(s.v)
+
+    def f():
+        m = m_val.clone().requires_grad_(True)
+        misfit(propagate(m, z, z, prob), d_obs).backward()
+    return f
+
+
 def gradient_checks(torch, mms, synth, prob, m, d_obs, grid, dev, npts=16, seed=84):
     """Central finite differences of J at 16 points drawn from the top decile of the
     (Gaussian-smoothed) |dJ/dm|, and a Taylor test along a smooth direction."""
@@ -725,10 +750,19 @@ COUNTED = {
     "vti": ("vti.hip", "vti_kernel<4", 36.0),                # 400^3 VTI step
     "tti_dz": ("tti.hip", "tti_dz_kernel<4", 24.0),          # 400^3 TTI pass 1 (padded rows)
     "tti": ("tti.hip", "tti_kernel<4", 60.0),                # 400^3 TTI pass 2
+    # 256^3 gradient workload: the mu-form adjoint pass (mu^{n+1}, mu^{n+2}, C2 read; mu^n
+    # written) and the gradient pass (u^n, mu^{n+1} read; FP32 block partial written at the
+    # first step of a block of 8, read and written in the next 6, read at the last, which
+    # reads and writes the FP64 sum: (12 + 6 * 16 + 28) / 8 = 17 B per point and launch)
+    "adjmu": ("wave.hip", "wave_kernel<4, 4, 64", 16.0),
+    "grad": ("wave.hip", "wave_kernel<4, 3, 64", 17.0),
 }
-COUNTED_POINTS = {"wave": 400 ** 3, "vti": 400 ** 3, "tti_dz": 400 ** 3, "tti": 400 ** 3}
-# the --only command that launches each counted kernel
-COUNTED_ONLY = {"tti_dz": "tti"}
+COUNTED_POINTS = {"wave": 400 ** 3, "vti": 400 ** 3, "tti_dz": 400 ** 3, "tti": 400 ** 3,
+                  "adjmu": 256 ** 3, "grad": 256 ** 3}
+# the --only command that launches each counted kernel, and its --steps / --warmup when the
+# defaults do not fit (one gradient run is 1000 forward and 1000 adjoint steps)
+COUNTED_ONLY = {"tti_dz": "tti", "adjmu": "gradient", "grad": "gradient"}
+ONLY_STEPS = {"gradient": ("1", "0")}
 
 
 def source_sha(fname):
@@ -838,10 +872,14 @@ def collect_counters(args):
         summary["trace_headline"][name] = {"avg_ns": ns, "calls": calls}
     # 1b. kernel traces of the single-kernel commands (split MFMA boxes, wave, VTI)
     summary["trace_only"] = {}
-    for name in ("box4_bf16x3", "box3_bf16x3", "wave", "vti", "tti_dz", "tti"):
-        d, cmd = prof(f"trace_{name}", ["--kernel-trace", "--stats"],
-                      ["--only", COUNTED_ONLY.get(name, name), "--steps", "200", "--warmup", "40"],
-                      120)
+    traced = {}
+    for name in ("box4_bf16x3", "box3_bf16x3", "wave", "vti", "tti_dz", "tti", "adjmu", "grad"):
+        only = COUNTED_ONLY.get(name, name)
+        if only not in traced:        # one run serves every kernel its command launches
+            st, wu = ONLY_STEPS.get(only, ("200", "40"))
+            traced[only] = prof(f"trace_{only}", ["--kernel-trace", "--stats"],
+                                ["--only", only, "--steps", st, "--warmup", wu], 120)
+        d, cmd = traced[only]
         ns, calls = _stats_mean_ns(find(d, "_kernel_stats.csv"), COUNTED[name][1])
         summary["trace_only"][name] = {"avg_ns": ns, "calls": calls, "command": cmd,
                                        "source_sha": source_sha(COUNTED[name][0])}
@@ -850,12 +888,16 @@ def collect_counters(args):
     sy = ((n + 8 + 31) // 32) * 32                      # the headline layout (Grid.aligned)
     grid_bytes = (n + 8) * (n + 8) * sy * 4             # one padded FP32 grid
     factors = {}
+    counted = {}
     for name, (src, sym, bpp) in COUNTED.items():
         e = {"source": src, "source_sha": source_sha(src), "symbol": sym}
+        only = COUNTED_ONLY.get(name, name)
         for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
-            d, cmd = prof(f"{name}_{ctr}", ["--pmc", ctr], ["--only", COUNTED_ONLY.get(name, name),
-                                                             "--steps", "3",
-                                                             "--warmup", "1"], 90)
+            if (only, ctr) not in counted:
+                st, wu = ONLY_STEPS.get(only, ("3", "1"))
+                counted[(only, ctr)] = prof(f"{only}_{ctr}", ["--pmc", ctr],
+                                            ["--only", only, "--steps", st, "--warmup", wu], 90)
+            d, cmd = counted[(only, ctr)]
             kib, cnt = _counter_mean(find(d, "_counter_collection.csv"), sym)
             e[ctr.lower() + "_kib"] = kib
             summary["commands"][f"{name}_{ctr}"] = cmd
@@ -965,6 +1007,8 @@ def profile_only(args, torch, mms, synth, grid, x, outs, sweeps, c_box4, c_box3,
             w.vti_step(i, ta, tb, H[(i - 1) % 2], H[i % 2], H[(i + 1) % 2],
                        V[(i - 1) % 2], V[i % 2], V[(i + 1) % 2])
             it[0] += 1
+    elif k == "gradient":
+        f = gradient_pass(torch, mms, synth, dev)
     elif k == "wave":
         n = 400
         s = synth.wave_setup(n, 64, seed=7, sponge_width=32)
