@@ -236,8 +236,12 @@ int mms_tti_step(const mms_wave *w, const mms_tti *t, int n, const float *p_prev
  * outputs (a HOST array of device pointers; entries may repeat as in mms_wave_adjoint).
  * With grad: grad += c2_scale G lam^{n+1} S(u^n) for n = max(n_lo, 1) .. n_hi, the same
  * terms as mms_wave_adjoint, formed as mu^{n+1} S(u^n) / c2; acc_block blocks as there.
- * Requires c2 > 0 in every interior cell (lam = mu / (C2 G)); results are undefined
- * otherwise.  Buffers are checked before anything is enqueued.
+ * grad is multiplied by c2 on entry and divided by it on exit (the per-step terms then
+ * need no c2 operand); the FP32 block partial holds mu^{n+1} S(u^n) sums, so a block
+ * begun by this call must be finished by calls of this entry point (and one begun by
+ * mms_wave_adjoint by that one).  Requires c2 > 0 in every interior cell
+ * (lam = mu / (C2 G)); results are undefined otherwise.  Buffers are checked before
+ * anything is enqueued.
  */
 int mms_wave_adjoint_mu(const mms_wave *w, int n_hi, int n_lo, float *const *mus,
                         const float *const *us, const float *resid, double *grad, void *stream);
