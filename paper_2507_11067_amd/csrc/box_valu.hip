@@ -16,6 +16,8 @@
 //  * a lane reads 12 consecutive cells of one input row (three 16-byte LDS
 //    words) and applies all (2r+1) x (2r+1) weights of that dy to them, so LDS
 //    traffic is 3 words per (2r+1)^2 * 4 FMAs.
+//  * the next input plane is requested from memory one plane ahead, two planes
+//    ahead at radius 1, where one plane's FMAs are too few to cover the latency.
 // Where the weights come from sets the FMA rate on gfx950: an FMA that reads
 // one operand from a scalar register issues at about 75 TFLOP/s chip-wide,
 // one with all operands in vector registers at about 110.  From radius 2 on
@@ -81,19 +83,25 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
         l_ok[k] = (i < NL) && (yy < ylim) && (xx <= nx4);
         l_off[k] = (int64_t)yy * sy + xx;
     }
-    float4 stage[NLK];
-    auto load_plane = [&](int z) {
+    // staged input planes in flight: radius 1 is bound by HBM and keeps two planes of
+    // requests outstanding (one plane's work does not cover the latency of the next
+    // plane's loads); from radius 2 on one plane of FMAs does
+    constexpr int NSB = R == 1 ? 2 : 1;
+    float4 stage[NSB][NLK];
+    auto load_plane = [&](int z, auto S) {
         const float *p = g.in0 + (int64_t)z * sz;
 #pragma unroll
         for (int k = 0; k < NLK; ++k)
-            stage[k] = guarded_load(p + l_off[k], l_ok[k], g.in0);
+            stage[decltype(S)::value][k] = guarded_load(p + l_off[k], l_ok[k], g.in0);
     };
-    auto store_plane = [&](int buf) {
+    auto store_plane = [&](int buf, auto S) {
         float4 *t = &tile[buf][0][0];
 #pragma unroll
         for (int k = 0; k < NLK; ++k)
-            if (tid + k * NT < NL) t[tid + k * NT] = stage[k];
+            if (tid + k * NT < NL) t[tid + k * NT] = stage[decltype(S)::value][k];
     };
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, NSB - 1>;
 
     float acc[W][4];
 #pragma unroll
@@ -102,13 +110,20 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
         for (int e = 0; e < 4; ++e) acc[s][e] = 0.f;
 
     const int z_first = zb - R, z_last = ze + R;  // input planes [z_first, z_last)
-    load_plane(z_first);
-    store_plane(0);
+    load_plane(z_first, S0{});
+    store_plane(0, S0{});
+    if (NSB == 2 && z_first + 1 < z_last) load_plane(z_first + 1, S1{});
     __syncthreads();
-    int buf = 0;
-    for (int zi = z_first; zi < z_last; ++zi) {
+    // one input plane zi, held in tile[buf]; with two staged planes, stage[SP] held plane zi
+    // (already in tile[buf]) and receives plane zi + 2, stage[SP ^ 1] holds plane zi + 1
+    auto step = [&](int zi, int buf, auto SP) {
+        constexpr int sp = decltype(SP)::value;
         const bool more = zi + 1 < z_last;
-        if (more) load_plane(zi + 1);
+        if constexpr (NSB == 2) {
+            if (zi + 2 < z_last) load_plane(zi + 2, SP);
+        } else {
+            if (more) load_plane(zi + 1, S0{});
+        }
         const float4 *t = &tile[buf][0][0];
         // Input planes within r of the chunk's ends feed some output planes outside
         // it; those (dz) terms are skipped there.  Every other plane feeds all 2r+1
@@ -162,9 +177,23 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
             for (int e = 0; e < 4; ++e) acc[s][e] = acc[s + 1][e];
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[W - 1][e] = 0.f;
-        if (more) store_plane(buf ^ 1);
+        if (more) store_plane(buf ^ 1, std::integral_constant<int, NSB == 2 ? (sp ^ 1) : 0>{});
         __syncthreads();
-        buf ^= 1;
+    };
+    if constexpr (NSB == 2) {
+        // the staging slot must be a compile-time index: planes in pairs
+        int zi = z_first;
+        for (; zi + 1 < z_last; zi += 2) {
+            step(zi, 0, S0{});
+            step(zi + 1, 1, S1{});
+        }
+        if (zi < z_last) step(zi, 0, S0{});
+    } else {
+        int buf = 0;
+        for (int zi = z_first; zi < z_last; ++zi) {
+            step(zi, buf, S0{});
+            buf ^= 1;
+        }
     }
     (void)ylim;
 }
