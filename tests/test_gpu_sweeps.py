@@ -222,19 +222,20 @@ def test_box_512_sampled(mms, big512, r, prec):
         assert rmax <= TOL, rmax
 
 
-@pytest.mark.parametrize("dims", [(64, 64, 64), (300, 9, 13), (133, 37, 20)],
-                         ids=lambda d: "x".join(map(str, d)))
+@pytest.mark.parametrize("dims", [(64, 64, 64, 4), (300, 9, 13, 4), (133, 37, 20, 4),
+                                  (37, 19, 11, 8)],
+                         ids=lambda d: "x".join(map(str, d[:3])) + f"-H{d[3]}")
 def test_aligned_layout_bit_identical(mms, dims):
     """Sweeps on the 128-byte-row layout (Grid.aligned with zeros()'s placement) against the
     default layout: the same kernels at other addresses, so the interiors are bit-identical
     and the halo stays unwritten; the star is also checked against the oracle."""
-    nx, ny, nz = dims
-    ga, gd = mms.Grid.aligned(nx, ny, nz), mms.Grid(nx, ny, nz)
-    xa_np = synth.uniform_grid(7, nx, ny, nz, sy=ga.sy)
+    nx, ny, nz, H = dims
+    ga, gd = mms.Grid.aligned(nx, ny, nz, H), mms.Grid(nx, ny, nz, H)
+    xa_np = synth.uniform_grid(7, nx, ny, nz, halo=H, sy=ga.sy)
     xa = ga.zeros(DEV)
     xa.copy_(torch.from_numpy(xa_np))
     assert (xa.data_ptr() + 4 * ga.halo * (ga.sz + ga.sy + 1)) % 128 == 0
-    xd = torch.from_numpy(synth.uniform_grid(7, nx, ny, nz, sy=gd.sy)).to(DEV)
+    xd = torch.from_numpy(synth.uniform_grid(7, nx, ny, nz, halo=H, sy=gd.sy)).to(DEV)
     rng = np.random.default_rng(8)
     cases = [("star", 4, synth.star_coeffs_random(9, 4), "fp32"),
              ("box", 1, synth.box_coeffs(10, 1), "fp32"),
@@ -254,6 +255,6 @@ def test_aligned_layout_bit_identical(mms, dims):
         interior(h, ga)[...] = 7.0
         assert np.all(h == 7.0), (shape, r, prec)
         if shape == "star":
-            ref = oracle.star(xa_np, nx, ny, nz, r, c)
+            ref = oracle.star(xa_np, nx, ny, nz, r, c, halo=H)
             rmax, _ = rel_errors(interior(a, ga), interior(ref, ga))
             assert rmax <= TOL, rmax
