@@ -556,6 +556,30 @@ def bench_gradient(torch, mms, synth, dev, n=256, nt=1000, K=50):
            "recomputed_steps": prob.stats.get("recomputed_steps"),
            "adjoint_form": prob.stats.get("adjoint_form")}
     log(f"[bench] gradient: fwd {fwd_ms:.0f} ms, bwd {bwd_ms:.0f} ms")
+    # the same gradient with every forward level resident (nt + 1 grids in HBM, no recompute):
+    # the trade that one GPU's 288 GB allows at this size; one untimed pass first as above
+    prob.store_all = True
+    mw = mgrid(s.v).requires_grad_(True)
+    misfit(propagate(mw, z, z, prob), d_obs).backward()
+    mw = mgrid(s.v).requires_grad_(True)
+    torch.cuda.synchronize()
+    a.record()
+    J2 = misfit(propagate(mw, z, z, prob), d_obs)
+    b.record()
+    J2.backward()
+    c.record()
+    torch.cuda.synchronize()
+    f2, b2 = a.elapsed_time(b), b.elapsed_time(c)
+    gdiff = float(((mw.grad - m.grad).abs().max() / m.grad.abs().max()).item())
+    res["store_all"] = {"forward_ms": f2, "backward_ms": b2,
+                        "gpoints_s": pts / ((f2 + b2) * 1e-3) / 1e9,
+                        "resident_gb": (nt + 1) * grid.shape[0] * grid.shape[1] * grid.shape[2] * 4 / 1e9,
+                        "recomputed_steps": prob.stats.get("recomputed_steps"),
+                        "grad_rel_diff_vs_checkpointed": gdiff}
+    prob.store_all = False
+    del mw, J2
+    log(f"[bench] gradient, all levels resident: fwd {f2:.0f} ms, bwd {b2:.0f} ms "
+        f"(gradient rel diff vs checkpointed {gdiff:.1e})")
     # dot-product test of the adjoint at the full size: A (u0, u1) -> traces (no source),
     # tested against y = the misfit residual of the gradient run (a smooth trace field)
     y = torch.empty_like(traces)

@@ -14,7 +14,10 @@ k = 0, K, 2K, ... .  The backward pass walks the segments [k, k+K) from the
 last to the first: it restores the pair, recomputes u^{k+2} .. u^{k+K-1} into
 a K-level buffer, then runs the adjoint steps k+K-1 .. k, which read u^n from
 that buffer and accumulate the FP64 gradient.  Extra cost: one more forward
-sweep; extra memory: 2 nt/K + K grids.
+sweep; extra memory: 2 nt/K + K grids.  With Problem.store_all the forward
+pass writes every level into a grid of its own instead (nt + 1 grids, 74 GB
+for 256^3 x 1000 steps, within one MI355X's 288 GB) and the backward pass
+runs the adjoint over all steps in one call with no recompute.
 
 Misfit.apply(traces, d_obs) -> J = 0.5 sum (d - d_obs)^2 (FP64, one element),
 computed and differentiated by the library's reduction kernel.
@@ -43,6 +46,7 @@ class Problem:
     checkpoint_every: int = 50
     grad_block: int = 8        # adjoint steps whose gradient terms are summed in FP32
     adjoint_form: str = "auto"  # "mu" (needs m > 0 on the interior), "lam", or "auto"
+    store_all: bool = False    # keep every forward level resident (nt + 1 grids), no recompute
     stats: dict = field(default_factory=dict)
 
     @property
@@ -65,17 +69,28 @@ class WavePropagate(torch.autograd.Function):
         m = m.detach().contiguous()
         traces = torch.zeros((nt, g.ny, g.nx), dtype=torch.float32, device=m.device)
         w = prob.wave(m, traces)
-        bufs = [u0.detach().clone(), u1.detach().clone(), g.zeros(m.device)]
-        if nt > 0:
-            w.record(0, bufs[0])
-        ckpts = []
-        for k in range(0, nt, K):
-            ckpts.append((bufs[k % 3].clone(), bufs[(k + 1) % 3].clone()))
-            n_end = min(k + K + 1, nt)
-            if n_end > k + 1:
-                w.forward(k + 1, n_end, [bufs[(k + i) % 3] for i in range(n_end - k + 1)])
+        ckpts, levels = [], None
+        if prob.store_all:
+            # level n in levels[n]; step nt-1 writes u^nt, which nothing reads
+            levels = [g.zeros(m.device) for _ in range(nt + 1)]
+            levels[0].copy_(u0.detach())
+            if nt > 0:
+                levels[1].copy_(u1.detach())
+                w.record(0, levels[0])
+            if nt > 1:
+                w.forward(1, nt, levels)
+        else:
+            bufs = [u0.detach().clone(), u1.detach().clone(), g.zeros(m.device)]
+            if nt > 0:
+                w.record(0, bufs[0])
+            for k in range(0, nt, K):
+                ckpts.append((bufs[k % 3].clone(), bufs[(k + 1) % 3].clone()))
+                n_end = min(k + K + 1, nt)
+                if n_end > k + 1:
+                    w.forward(k + 1, n_end, [bufs[(k + i) % 3] for i in range(n_end - k + 1)])
         ctx.prob = prob
         ctx.ckpts = ckpts
+        ctx.levels = levels
         ctx.save_for_backward(m)
         prob.stats["forward_steps"] = max(nt - 1, 0)
         return traces
@@ -99,13 +114,17 @@ class WavePropagate(torch.autograd.Function):
         mu_form = positive
         adjoint = wa.adjoint_mu if mu_form else wa.adjoint
         lam = [g.zeros(dev) for _ in range(3)]   # lam^n (or mu^n) lives in lam[n % 3]
-        seg = [g.zeros(dev) for _ in range(min(K, max(nt, 1)))]
+        seg = [] if ctx.levels is not None else [g.zeros(dev) for _ in range(min(K, max(nt, 1)))]
         grad = torch.zeros((g.nz, g.ny, g.nx), dtype=torch.float64, device=dev)
         if prob.grad_block > 1:
             # each block of grad_block adjoint steps is summed in FP32, then added in FP64
             wa.set_accumulation(torch.empty((g.nz, g.ny, g.nx), device=dev), prob.grad_block)
         recomputed = 0
         w_src = prob.wave(m)               # recompute: same source, no receivers
+        if ctx.levels is not None and nt > 0:
+            # every level is resident: the whole adjoint in one call
+            adjoint(nt - 1, 0, [lam[i % 3] for i in range(nt + 2)], us=ctx.levels[0:nt],
+                    resid=resid, grad=grad)
         for si in range(len(ctx.ckpts) - 1, -1, -1):
             k = si * K
             hi = min(k + K, nt) - 1
@@ -124,6 +143,7 @@ class WavePropagate(torch.autograd.Function):
         grad_u0 = lam[0].clone() if nt > 0 else g.zeros(dev)
         grad_u1 = lam[1 % 3].clone() if nt > 1 else g.zeros(dev)
         prob.stats["recomputed_steps"] = recomputed
+        ctx.levels = None
         prob.stats["adjoint_form"] = "mu" if mu_form else "lam"
         ctx.ckpts = None
         return grad_m, grad_u0, grad_u1, None

@@ -248,17 +248,19 @@ def autograd_problem(mms, n, nt, seed, K, W=8):
 
 @pytest.mark.parametrize("form", ["lam", "mu"])
 def test_checkpointing_gives_identical_gradient(mms, form):
-    """Segment length changes only where the forward levels come from: the lam-form gradient
-    is bit-identical; the mu form scales the FP64 sum by c2 and back once per segment, so its
-    FP64 sums may differ in the last bits, which FP32 output hides or shows as one ulp."""
+    """Segment length, or keeping every level resident (store_all, no recompute), changes only
+    where the forward levels come from: the lam-form gradient is bit-identical; the mu form
+    scales the FP64 sum by c2 and back once per segment, so its FP64 sums may differ in the
+    last bits, which FP32 output hides or shows as one ulp."""
     from paper_2507_11067_amd.autograd import misfit, propagate
     n, nt = 32, 120
     s, grid, m, prob = autograd_problem(mms, n, nt, 40, K=50)
     prob.adjoint_form = form
     d_obs = torch.zeros((nt, n, n), device=DEV)
     grads = []
-    for K in (50, 7, 1000):
-        prob.checkpoint_every = K
+    for K in (50, 7, 1000, "all"):
+        prob.store_all = K == "all"
+        prob.checkpoint_every = 50 if K == "all" else K
         mt = T(m).requires_grad_(True)
         z0 = grid.zeros(DEV).requires_grad_(True)
         z1 = grid.zeros(DEV).requires_grad_(True)
@@ -274,6 +276,7 @@ def test_checkpointing_gives_identical_gradient(mms, form):
                 assert (a - b).abs().max() <= ulp
     assert torch.count_nonzero(grads[0][0]) > 0
     assert prob.stats["adjoint_form"] == form
+    assert prob.stats["recomputed_steps"] == 0          # the store_all pass recomputed nothing
 
 
 def test_gradient_mu_form_matches_lambda_form(mms):
