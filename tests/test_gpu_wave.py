@@ -502,3 +502,36 @@ def test_aligned_layout_wave_bit_identical(mms):
     for a, b in zip(*out):
         assert np.abs(a).max() > 0
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("nt", [1, 2, 3])
+def test_gradient_few_steps_all_modes(mms, nt):
+    """A handful of time levels (the first adjoint step, a lone block tail): the gradient and
+    dJ/du0, dJ/du1 agree across the checkpointed lam form, the checkpointed mu form and the
+    all-levels-resident mode, and dJ/du0 matches the closed form lam^0 = R^T r^0 - G^2 lam^2."""
+    from paper_2507_11067_amd.autograd import misfit, propagate
+    n = 24
+    s, grid, m, prob = autograd_problem(mms, n, nt, 46, K=2)
+    d_obs = T(np.random.default_rng(47).standard_normal((nt, n, n)) * 1e-3)
+    u0, u1 = T(smooth(48, grid)), T(smooth(49, grid))
+    out = []
+    for form, store_all in (("lam", False), ("mu", False), ("mu", True)):
+        prob.adjoint_form, prob.store_all = form, store_all
+        mt = T(m).requires_grad_(True)
+        z0 = u0.clone().requires_grad_(True)
+        z1 = u1.clone().requires_grad_(True)
+        traces = propagate(mt, z0, z1, prob)
+        J = misfit(traces, d_obs)
+        J.backward()
+        out.append([interior(t.grad.cpu().numpy(), grid) for t in (mt, z0, z1)])
+        resid0 = (traces[0] - d_obs[0]).detach().cpu().numpy()
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            rmax, _ = rel_errors(b, a)
+            assert rmax <= 1e-5, (nt, rmax)
+    if nt == 1:
+        # lam^2 = 0: dJ/du0 is the receiver residual on the top plane, zero below
+        g0 = out[0][1]
+        assert np.allclose(g0[0], resid0, rtol=1e-6, atol=1e-12)
+        assert not np.any(g0[1:])
+        assert not np.any(out[0][0]) and not np.any(out[0][2])
