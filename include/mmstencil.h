@@ -237,7 +237,8 @@ int mms_tti_step(const mms_wave *w, const mms_tti *t, int n, const float *p_prev
  * With grad: grad += c2_scale G lam^{n+1} S(u^n) for n = max(n_lo, 1) .. n_hi, the same
  * terms as mms_wave_adjoint, formed as mu^{n+1} S(u^n) / c2; acc_block blocks as there.
  * grad is multiplied by c2 on entry and divided by it on exit (the per-step terms then
- * need no c2 operand); the FP32 block partial holds mu^{n+1} S(u^n) sums, so a block
+ * need no c2 operand; if a launch fails in between, MMS_EHIP is returned and grad is
+ * left in the scaled units); the FP32 block partial holds mu^{n+1} S(u^n) sums, so a block
  * begun by this call must be finished by calls of this entry point (and one begun by
  * mms_wave_adjoint by that one).  Requires c2 > 0 in every interior cell
  * (lam = mu / (C2 G)); results are undefined otherwise.  Buffers are checked before
