@@ -129,11 +129,12 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
         // it; those (dz) terms are skipped there.  Every other plane feeds all 2r+1
         // accumulators, and that path has no per-dz test.
         auto plane = [&](auto checked) {
-            // dy stays a loop: unrolled with scalar-register weights, all (2r+1)^3
+            // dy stays a loop with scalar-register weights: unrolled, all (2r+1)^3
             // would be hoisted into scalar registers and spill to vector-register
-            // lanes.  With LDS weights at radius 2 the unrolled loop is 3 % faster
-            // (282 -> 290 Gpoints/s at 512^3); at radius 3 and 4 it gains nothing.
-            constexpr int DYU = (LDSW && R == 2) ? 2 * R + 1 : 1;
+            // lanes.  With LDS weights the unrolled loop is faster at radius 2 and 4
+            // (282 -> 290 and 66.4 -> 69.1 Gpoints/s at 512^3; 119 VGPRs at radius 4,
+            // still 4 waves per SIMD) and gains nothing at radius 3.
+            constexpr int DYU = (LDSW && (R == 2 || R == 4)) ? 2 * R + 1 : 1;
 #pragma unroll DYU
             for (int dy = -R; dy <= R; ++dy) {
                 const float4 *row = t + (ty + R + dy) * LW4;
