@@ -214,6 +214,8 @@ class Wave:
         g = self.grid
         if len(lams) < n_hi - n_lo + 3:
             raise ValueError("lams too short")
+        if us is not None and len(us) < n_hi - n_lo + 1:
+            raise ValueError("us too short")
         la = (ctypes.c_void_p * len(lams))(*[_grid_ptr(t, g, "lam") for t in lams])
         ua = None
         if us is not None:
@@ -229,6 +231,8 @@ class Wave:
         g = self.grid
         if len(mus) < n_hi - n_lo + 3:
             raise ValueError("mus too short")
+        if us is not None and len(us) < n_hi - n_lo + 1:
+            raise ValueError("us too short")
         ma = (ctypes.c_void_p * len(mus))(*[_grid_ptr(t, g, "mu") for t in mus])
         ua = None
         if us is not None:

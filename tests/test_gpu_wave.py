@@ -535,3 +535,17 @@ def test_gradient_few_steps_all_modes(mms, nt):
         assert np.allclose(g0[0], resid0, rtol=1e-6, atol=1e-12)
         assert not np.any(g0[1:])
         assert not np.any(out[0][0]) and not np.any(out[0][2])
+
+
+def test_adjoint_bindings_reject_short_lists(mms):
+    """The host arrays of levels handed to the C ABI cover every step of the range."""
+    grid, w, lam_top, us, resid = mu_problem(mms, 12, 10, 9, 6, 80, W=2)
+    bufs = [grid.zeros(DEV) for _ in range(8)]
+    grad = torch.zeros((9, 10, 12), dtype=torch.float64, device=DEV)
+    for f in (w.adjoint, w.adjoint_mu):
+        with pytest.raises(ValueError, match="us too short"):
+            f(5, 0, bufs, us=us[:5], resid=resid, grad=grad)
+        with pytest.raises(ValueError, match="too short"):
+            f(5, 0, bufs[:7], us=us, resid=resid, grad=grad)
+        f(5, 0, bufs, us=us, resid=resid, grad=grad)      # the full lists are accepted
+    torch.cuda.synchronize()
