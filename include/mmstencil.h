@@ -34,7 +34,7 @@
 extern "C" {
 #endif
 
-#define MMS_ABI_VERSION 2
+#define MMS_ABI_VERSION 3   /* 3: mms_wave_adjoint_mu, mms_wave_scale_mu, mms_grid_aligned */
 
 /* error codes */
 #define MMS_OK 0

@@ -31,7 +31,7 @@ def test_header_symbols_exported(L):
 
 
 def test_version_and_strerror(L):
-    assert L.mms_abi_version() == 2
+    assert L.mms_abi_version() == 3
     for code in (0, -1, -2, -3, -4):
         assert L.mms_strerror(code)
 
