@@ -339,6 +339,30 @@ def test_box_separable_and_r1_star():
                                atol=1e-14)
 
 
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
+def test_sampled_definitions_match_full_grid_sweeps(r):
+    """The point-list evaluators (star_at, box_at and the 2-D ones) return what the
+    full-grid sweeps (pinned above to scipy, the dense operator and exact
+    derivatives) return at the same points: non-symmetric weights, a non-zero halo,
+    points on every face and corner of the interior as well as random ones."""
+    nx, ny, nz = 13, 9, 11
+    rng = np.random.default_rng(40 + r)
+    a = synth.padded_zeros(nx, ny, nz, dtype=np.float64)
+    a[...] = rng.uniform(-1, 1, a.shape)
+    w = 2 * r + 1
+    pts = [(z, y, x) for z in (0, nz - 1) for y in (0, ny - 1) for x in (0, nx - 1)]
+    pts += [tuple(int(v) for v in rng.integers(0, (nz, ny, nx))) for _ in range(200)]
+    pts = np.array(pts)
+    I = lambda f: synth.interior(f, nx, ny, nz)[pts[:, 0], pts[:, 1], pts[:, 2]]
+    cases = [(oracle.star_at, oracle.star, (3, w)), (oracle.box_at, oracle.box, (w, w, w)),
+             (oracle.star2d_at, oracle.star2d, (2, w)), (oracle.box2d_at, oracle.box2d, (w, w))]
+    for at, full, cshape in cases:
+        c = rng.uniform(-1, 1, cshape)
+        want = I(full(a, nx, ny, nz, r, c))
+        got = at(a, nx, ny, nz, r, c, pts)
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-14 * np.abs(want).max())
+
+
 # ------------------------------------------------------------------ sponge
 def test_sponge_profile_closed_form():
     g = oracle.sponge_1d(100, 32, 0.015, True, True)
@@ -516,6 +540,29 @@ def test_forward_step_matches_run_and_records_traces():
     assert d[2 + 4, n // 2 + 4, n // 2 + 4] == pytest.approx(f[3], rel=1e-12)
     d[2 + 4, n // 2 + 4, n // 2 + 4] = 0
     assert np.max(np.abs(d)) == 0
+
+
+def test_image_is_sum_of_squared_new_levels():
+    """The forward run's image is sum over the steps n = 1..nt-1 of (u^{n+1})^2 (the
+    level each step produces, not the level it reads), summed here in numpy from the
+    stored states; the halo stays zero."""
+    n, nt = 10, 9
+    rng = np.random.default_rng(34)
+    w = sponge_problem(n, nt, seed=35, f=rng.standard_normal(nt))
+    u0 = synth.smooth_random_grid(36, n, n, n).astype(np.float64)
+    u1 = synth.smooth_random_grid(37, n, n, n).astype(np.float64)
+    res = w.forward(u0, u1, keep_states=True, image=True)
+    st = res["states"]             # st[k] = u^k, k = 0..nt
+    want = np.sum(st[2:nt + 1] ** 2, axis=0)
+    H = 4
+    np.testing.assert_allclose(synth.interior(res["image"], n, n, n), synth.interior(want, n, n, n),
+                               rtol=1e-14, atol=0)
+    mask = np.ones(w.shape, dtype=bool)
+    mask[H:H + n, H:H + n, H:H + n] = False
+    assert not np.any(res["image"][mask])
+    # the levels read (u^1 .. u^{nt-1}) give a different sum
+    wrong = np.sum(st[1:nt] ** 2, axis=0)
+    assert np.max(np.abs(synth.interior(wrong - want, n, n, n))) > 1e-3 * np.max(want)
 
 
 # ------------------------------------------------------------ VTI oracle
@@ -733,6 +780,48 @@ def test_tti_axis_along_x_is_transposed_vti():
     got = np.stack([T(a) for a in tt["last"]])
     scale = np.max(np.abs(vt["last"]))
     assert np.max(np.abs(got - vt["last"])) <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("axis", ["z", "x", "y"])
+def test_tti_shear_and_alpha_terms_sine_mode(axis):
+    """A constant medium whose symmetry axis lies along a grid axis, radius-1 weights
+    and a zero halo: H1 is then the second difference along that axis and H2 the sum
+    of the other two, and p = a Phi, q = b Phi on a sine eigenvector Phi stays a mode.
+    With -s1, -s2 the eigenvalues of H1, H2 on Phi, the printed pair gives
+      [a, b]^{n+1} = 2 [a, b]^n - [a, b]^{n-1} - C2 M [a, b]^n,
+      M = [[(1+2eps) s2 + sigma s1,          alpha (1 - sigma) s1],
+           [(1+2delta - sigma) s2 / alpha,   s1 + sigma s2       ]].
+    sigma > 0 and alpha != sqrt(1 + 2 delta) make every term of both equations count:
+    a sign flip of a sigma term, H1 and H2 exchanged inside one, or alpha moved from
+    the denominator of (1+2delta)/alpha changes M."""
+    n, nt = 11, 60
+    kz, ky, kx = 2, 3, 1
+    lam = lambda k: -4.0 * np.sin(np.pi * k / (2 * (n + 1))) ** 2
+    s_axis = {"z": -lam(kz), "y": -lam(ky), "x": -lam(kx)}
+    s1 = s_axis[axis]
+    s2 = sum(v for a, v in s_axis.items() if a != axis)
+    theta, phi = {"z": (0.0, 0.7), "x": (np.pi / 2, 0.0), "y": (np.pi / 2, np.pi / 2)}[axis]
+    eps, delta, sigma, alpha, c2_val = 0.2, 0.1, 0.25, 0.6, 0.2
+    i = np.arange(n)
+    mode = lambda k: np.sin(np.pi * k * (i + 1) / (n + 1))
+    Phi = mode(kz)[:, None, None] * mode(ky)[None, :, None] * mode(kx)[None, None, :]
+    pad = lambda x: np.pad(x, 4)
+    full = lambda v: pad(np.full((n, n, n), v))
+    w = oracle.Wave(n, n, n, full(c2_val), [-2.0, 1.0], (0, 0, 0), np.zeros(nt), nt)
+    t = w.tti(full(eps), full(delta), full(theta), full(phi), sigma, alpha, [0.5])
+    a0, b0 = [1.0, 0.95], [-0.4, -0.42]
+    res = w.tti_forward(t, pad(a0[0] * Phi), pad(a0[1] * Phi), pad(b0[0] * Phi), pad(b0[1] * Phi))
+    M = np.array([[(1 + 2 * eps) * s2 + sigma * s1, alpha * (1 - sigma) * s1],
+                  [(1 + 2 * delta - sigma) * s2 / alpha, s1 + sigma * s2]])
+    s_prev, s_cur = np.array([a0[0], b0[0]]), np.array([a0[1], b0[1]])
+    for _ in range(1, nt):
+        s_prev, s_cur = s_cur, 2 * s_cur - s_prev - c2_val * M @ s_cur
+    I = lambda x: synth.interior(x, n, n, n)
+    np.testing.assert_allclose(I(res["last"][1]), s_cur[0] * Phi, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(I(res["last"][3]), s_cur[1] * Phi, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(I(res["last"][0]), s_prev[0] * Phi, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(I(res["last"][2]), s_prev[1] * Phi, rtol=0, atol=1e-12)
+    assert abs(s_cur[0]) > 0.02 and abs(s_cur[1]) > 0.02
 
 
 def test_tti_step_matches_forward():
