@@ -10,7 +10,8 @@ is interior points swept per second over the timed steps (Gpoints/s).
 
 Besides the headline the same JSON line carries, each measured in this run:
   * "kernels": per-stencil Gpoints/s, achieved GB/s or TFLOP/s and the max /
-    RMS error against the FP64 oracle at 4000 sampled points;
+    RMS error against the FP64 oracle over every interior point;
+  * "config0": the 64^3 radius-4 Laplacian star, 10 repeated sweeps (time and error);
   * "split_mfma": the radius-4 and radius-3 boxes three ways (FP32 VALU, BF16x3
     and FP16x3S split MFMA, plus the BF16x1 error report);
   * "rtm": the 400^3, 2000-step acoustic forward model with FP64 imaging;
@@ -21,7 +22,12 @@ Besides the headline the same JSON line carries, each measured in this run:
   * "gradient": the 256^3, 1000-step adjoint gradient with checkpointing,
     with its dot-product test;
   * "roofline" of the dominant kernel and "cpu_baseline" (the FP64 oracle on
-    the host cores over a bounded sample of the headline workload).
+    the host cores over one step of the headline workload).
+
+The FP64 oracle runs only in the CPU-baseline leg: it times the oracle on one
+headline step and keeps those full-grid outputs (with untimed oracle sweeps of
+the other 512^3 kernels) as the references of every error column, so each
+error is over all 134,217,728 outputs of a sweep.
 
 Kernels run on torch's current stream; HIP events recorded on that stream
 bracket every launch, so per-kernel times come from the same events.
@@ -61,7 +67,6 @@ def parse():
                    "3DStarR2|3DBoxR1|tti")
     p.add_argument("--skip", default="", help="comma list of extras to skip: "
                    "split,table1,rtm,vti,tti,gradient,cpu,check")
-    p.add_argument("--cpu-planes", type=int, default=0, help="oracle sample depth (0 = full grid)")
     p.add_argument("--collect", action="store_true",
                    help="run rocprofv3 (kernel trace, FETCH_SIZE, WRITE_SIZE) as child processes "
                         "over the headline kernels and a plain copy, and write profiles/")
@@ -113,19 +118,6 @@ def time_launches(torch, f, warm_ms=60.0, min_ms=150.0):
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / reps
-
-
-def sample_points(n, count, seed):
-    rng = np.random.default_rng(seed)
-    pts = rng.integers(0, n, (count, 3))
-    edge = np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, n // 2], [n - 1, 0, 0]])
-    return np.concatenate([pts, edge])
-
-
-def errors(got, ref):
-    d = got.astype(np.float64) - ref
-    return (float(np.max(np.abs(d)) / np.max(np.abs(ref))),
-            float(np.linalg.norm(d) / np.linalg.norm(ref)))
 
 
 def main():
@@ -200,20 +192,6 @@ def main():
                          "tflops": gpts * flop_pt / 1e3,
                          "hbm_frac": gpts * bytes_pt / HBM_PEAK_GBS,
                          "valu_frac": gpts * flop_pt / 1e3 / FP32_VALU_PEAK_TF}
-    if "check" not in skip:
-        log("[bench] sampled parity vs FP64 oracle")
-        import oracle
-        x64 = x_np.astype(np.float64)
-        ptsel = sample_points(n, 4000, 14)
-        for name, r, c, fn in (("star", 4, c_star, oracle.star_at), ("box2", 2, c_box2, oracle.box_at),
-                               ("box4", 4, c_box4, oracle.box_at)):
-            ref = fn(x64, n, n, n, r, c, ptsel[:1000] if name == "box4" else ptsel)
-            o = outs[name].cpu().numpy()
-            sel = ptsel[:1000] if name == "box4" else ptsel
-            got = o[sel[:, 0] + 4, sel[:, 1] + 4, sel[:, 2] + 4]
-            kernels[name]["rel_max"], kernels[name]["rel_rms"] = errors(got, ref)
-        del x64
-
     # dominant kernel of the step: the radius-4 box (FP32 FMA bound)
     dom = max(kernels, key=lambda k: kernels[k]["ms"])
     kd = kernels[dom]
@@ -270,12 +248,15 @@ def main():
         "rooflines": rooflines,
         "kernels": kernels,
     }
+    result["config0"] = bench_config0(torch, mms, synth, dev)
     if "split" not in skip:
-        result["split_mfma"] = bench_split(torch, mms, synth, grid, x, x_np, n, c_box4, c_box3,
-                                           dev, "check" not in skip)
+        result["split_mfma"] = bench_split(torch, mms, grid, x, c_box4, c_box3, dev)
     if "table1" not in skip:
-        result["table1"] = bench_table1(torch, mms, synth, grid, x, x_np, n, dev,
-                                        "check" not in skip)
+        result["table1"] = bench_table1(torch, mms, synth, grid, x, dev)
+    if "cpu" not in skip:
+        result["cpu_baseline"] = cpu_baseline_leg(torch, mms, synth, grid, x, x_np, n, dev, result,
+                                                  c_star, c_box2, c_box4, c_box3,
+                                                  "check" not in skip)
     del outs
     if "rtm" not in skip:
         result["rtm"] = bench_rtm(torch, mms, synth, dev)
@@ -285,35 +266,33 @@ def main():
         result["tti"] = bench_tti(torch, mms, synth, dev)
     if "gradient" not in skip:
         result["gradient"] = bench_gradient(torch, mms, synth, dev)
-    if "cpu" not in skip:
-        result["cpu_baseline"] = cpu_baseline(x_np, n, c_star, c_box2, c_box4, args.cpu_planes)
     print(json.dumps(result), flush=True)
 
 
-def bench_split(torch, mms, synth, grid, x, x_np, n, c_box4, c_box3, dev, check):
-    """Radius-4 and radius-3 boxes at 512^3 three ways, with errors vs the FP64 oracle."""
-    import oracle
+def bench_split(torch, mms, grid, x, c_box4, c_box3, dev):
+    """Radius-4 and radius-3 boxes at 512^3 three ways (FP32 VALU, BF16x3 and FP16x3S split
+    MFMA, plus BF16x1); their errors against the FP64 oracle are added by the CPU leg."""
     out = grid.zeros(dev)
     res = {}
-    x64 = x_np.astype(np.float64) if check else None
-    sel = sample_points(n, 1000, 15)
     for r, c in ((4, c_box4), (3, c_box3)):
-        ref = oracle.box_at(x64, n, n, n, r, c, sel) if check else None
         for prec in ("fp32", "bf16x3", "fp16x3s", "bf16x1"):
             f = lambda: mms.stencil_apply(x, out, grid, "box", r, c, precision=prec)
             ms = time_launches(torch, f)
             gpts = grid.points / (ms * 1e-3) / 1e9
             e = {"ms": ms, "gpoints_s": gpts}
             flop = 2 * (2 * r + 1) ** 3
+            e["algorithmic_tflops"] = gpts * flop / 1e3
             if prec == "fp32":
                 e["valu_frac"] = gpts * flop / 1e3 / FP32_VALU_PEAK_TF
             else:
+                # the method's 2 (2r+1)^3 flop per point against the MFMA peak, and the
+                # issued 16x16x32 MFMA work (Toeplitz band, split products) beside it
                 nch = -(-((2 * r + 1) * 24) // 32)
                 mfma_per_tile = (3 if prec != "bf16x1" else 1) * (2 * r + 1) * nch
                 issued = gpts * 1e9 / 256 * mfma_per_tile * 16 * 16 * 32 * 2 / 1e12
+                e["mfma_algorithmic_frac"] = e["algorithmic_tflops"] / MFMA_BF16_PEAK_TF
                 e["mfma_issued_tflops"] = issued
-                e["mfma_frac"] = issued / MFMA_BF16_PEAK_TF
-                e["algorithmic_tflops"] = gpts * flop / 1e3
+                e["mfma_issued_frac"] = issued / MFMA_BF16_PEAK_TF
             u = util_for(f"box{r}_{prec}") if prec != "fp32" else None
             if u:
                 e["rocprof_mfma_util_pct"] = u.get("MfmaUtil")
@@ -321,18 +300,38 @@ def bench_split(torch, mms, synth, grid, x, x_np, n, c_box4, c_box3, dev, check)
                 if mops:
                     e["rocprof_mfma_tflops"] = mops * 512 / (ms * 1e-3) / 1e12
                 e["rocprof_lds_bank_conflict_pct"] = u.get("LDSBankConflict")
-            if check:
-                o = out.cpu().numpy()
-                got = o[sel[:, 0] + 4, sel[:, 1] + 4, sel[:, 2] + 4]
-                e["rel_max"], e["rel_rms"] = errors(got, ref)
             res[f"box_r{r}_{prec}"] = e
-            log(f"[bench] box r{r} {prec}: {gpts:.1f} Gpoints/s "
-                f"{'rel_max %.2e' % e['rel_max'] if 'rel_max' in e else ''}")
+            log(f"[bench] box r{r} {prec}: {gpts:.1f} Gpoints/s")
         res[f"box_r{r}_speedup_bf16x3_over_fp32"] = (res[f"box_r{r}_bf16x3"]["gpoints_s"] /
                                                      res[f"box_r{r}_fp32"]["gpoints_s"])
         res[f"box_r{r}_speedup_fp16x3s_over_fp32"] = (res[f"box_r{r}_fp16x3s"]["gpoints_s"] /
                                                       res[f"box_r{r}_fp32"]["gpoints_s"])
     return res
+
+
+def bench_config0(torch, mms, synth, dev, n=64, sweeps=10):
+    """The 64^3 radius-4 Laplacian star (4-cell zero halo, uniform [-1, 1], seed 1), 10
+    repeated out-of-place sweeps of the same input; its error is added by the CPU leg."""
+    grid = mms.Grid(n, n, n)
+    x = torch.from_numpy(synth.uniform_grid(1, n, n, n, sy=grid.sy)).to(dev)
+    out = grid.zeros(dev)
+    c = synth.star_coeffs_laplacian(4)
+    f = lambda: mms.stencil_apply(x, out, grid, "star", 4, c)
+    for _ in range(3):
+        f()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(sweeps):
+        f()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    gpts = sweeps * grid.points / (ms * 1e-3) / 1e9
+    log(f"[bench] config 0 (64^3 star r4, {sweeps} sweeps): {ms * 1e3:.1f} us, {gpts:.1f} Gpoints/s")
+    return {"grid": [n, n, n], "sweeps": sweeps, "ms_total": ms, "us_per_sweep": ms * 1e3 / sweeps,
+            "gpoints_s": gpts,
+            "note": "1 MB grid: launch- and cache-bound, a correctness config"}
 
 
 def bench_rtm(torch, mms, synth, dev, n=400, nt=2000):
@@ -394,15 +393,11 @@ def table1_kernels(synth):
     }
 
 
-def bench_table1(torch, mms, synth, grid, x, x_np, n, dev, check):
-    """Every Table I kernel on the 512^3 grid (2-D kernels on each of its planes), FP32."""
-    import oracle
+def bench_table1(torch, mms, synth, grid, x, dev):
+    """Every Table I kernel on the 512^3 grid (2-D kernels on each of its planes), FP32; the
+    errors against the FP64 oracle are added by the CPU leg."""
     out = grid.zeros(dev)
     res = {}
-    x64 = x_np.astype(np.float64) if check else None
-    sel = sample_points(n, 1000, 16)
-    at = {"star": oracle.star_at, "box": oracle.box_at, "star2d": oracle.star2d_at,
-          "box2d": oracle.box2d_at}
     for name, (shape, r, c, pattern) in table1_kernels(synth).items():
         f = lambda: mms.stencil_apply(x, out, grid, shape, r, c)
         ms = time_launches(torch, f)
@@ -412,10 +407,6 @@ def bench_table1(torch, mms, synth, grid, x, x_np, n, dev, check):
         e = {"shape": shape, "radius": r, "points": int(npts), "table_pattern": pattern,
              "ms": ms, "gpoints_s": gpts, "gbs": gpts * 8.0, "hbm_frac": gpts * 8.0 / HBM_PEAK_GBS,
              "tflops": gpts * flop / 1e3, "valu_frac": gpts * flop / 1e3 / FP32_VALU_PEAK_TF}
-        if check:
-            o = out.cpu().numpy()
-            got = o[sel[:, 0] + 4, sel[:, 1] + 4, sel[:, 2] + 4]
-            e["rel_max"], e["rel_rms"] = errors(got, at[shape](x64, n, n, n, r, c, sel))
         res[name] = e
         log(f"[bench] {name}: {gpts:.1f} Gpoints/s, {e['gbs']:.0f} GB/s ({e['hbm_frac']:.2f} "
             f"HBM), {e['tflops']:.1f} TFLOP/s")
@@ -642,7 +633,7 @@ def gradient_checks(torch, mms, synth, prob, m, d_obs, grid, dev, npts=16, seed=
     n, nt = grid.nx, prob.nt
     traces = torch.zeros((nt, grid.ny, grid.nx), device=dev)
     bufs = [grid.zeros(dev) for _ in range(3)]
-    jout = torch.zeros(1, dtype=torch.float64, device=dev)
+    jout = torch.zeros(2, dtype=torch.float64, device=dev)
 
     def J_of(mt):
         w = prob.wave(mt, traces)
@@ -650,7 +641,7 @@ def gradient_checks(torch, mms, synth, prob, m, d_obs, grid, dev, npts=16, seed=
             b_.zero_()
         w.record(0, bufs[0])
         w.forward(1, nt, [bufs[i % 3] for i in range(nt + 1)])
-        return mms.flat_misfit(traces, d_obs, out=jout).item()
+        return mms.check_result(mms.flat_misfit(traces, d_obs, out=jout))
 
     g = m.grad.detach()
     gi = grid.interior(g).cpu().numpy()
@@ -737,26 +728,99 @@ def gradient_checks(torch, mms, synth, prob, m, d_obs, grid, dev, npts=16, seed=
     return fdres, {"J0": J0, "g_dot_dm": gdm, "rows": rows}
 
 
-def cpu_baseline(x_np, n, c_star, c_box2, c_box4, planes):
-    """FP64 oracle on the host cores over a slab of the headline input."""
+def errors_chunked(got, ref, chunk=32):
+    """Normwise (max, RMS) errors of two [z][y][x] arrays, accumulated over z chunks in FP64."""
+    dmax = rmax = dss = rss = 0.0
+    for z0 in range(0, got.shape[0], chunk):
+        g = np.asarray(got[z0:z0 + chunk], dtype=np.float64)
+        r = np.asarray(ref[z0:z0 + chunk], dtype=np.float64)
+        d = g - r
+        dmax = max(dmax, float(np.max(np.abs(d))))
+        rmax = max(rmax, float(np.max(np.abs(r))))
+        dss += float(np.sum(d * d))
+        rss += float(np.sum(r * r))
+    return dmax / rmax, float(np.sqrt(dss / rss))
+
+
+def cpu_baseline_leg(torch, mms, synth, grid, x, x_np, n, dev, result, c_star, c_box2, c_box4,
+                     c_box3, check):
+    """The FP64 oracle on the host cores.  (a) Timed: one step of the headline workload (star
+    r4, box r2, box r4) over the full 512^3 grid -- the cpu_baseline figure.  (b) Untimed
+    unless already computed: full-grid oracle sweeps of every other 512^3 kernel of this run.
+    Each GPU sweep is run again into a scratch grid and compared with its reference at every
+    interior point; the errors go into the kernels / split_mfma / table1 / config0 entries."""
     import oracle
-    nz = planes if planes > 0 else n
-    nz = min(nz, n)
-    slab = np.ascontiguousarray(x_np[:nz + 8].astype(np.float64))  # planes -4 .. nz+3
     cores = len(os.sched_getaffinity(0))
     threads = int(os.environ.get("OMP_NUM_THREADS", cores))
-    log(f"[bench] cpu baseline: oracle on {n}x{n}x{nz} slab, {threads} threads")
+    x64 = x_np.astype(np.float64)
+    I = lambda a: a[4:4 + n, 4:4 + n, 4:4 + n]
+    out = grid.zeros(dev)
+
+    def gpu(shape, r, c, prec="fp32"):
+        mms.stencil_apply(x, out, grid, shape, r, c, precision=prec)
+        torch.cuda.synchronize()
+        return I(out.cpu().numpy())
+
+    def record(entry, shape, r, c, ref, prec="fp32"):
+        if entry is not None:
+            entry["rel_max"], entry["rel_rms"] = errors_chunked(gpu(shape, r, c, prec), ref)
+            entry["error_points"] = n ** 3
+
+    log(f"[bench] cpu baseline: oracle, one headline step over {n}^3, {threads} threads")
     t0 = time.perf_counter()
-    oracle.star(slab, n, n, nz, 4, c_star)
-    oracle.box(slab, n, n, nz, 2, c_box2)
-    oracle.box(slab, n, n, nz, 4, c_box4)
+    refs = {"star": oracle.star(x64, n, n, n, 4, c_star)}
+    refs["box2"] = oracle.box(x64, n, n, n, 2, c_box2)
+    refs["box4"] = oracle.box(x64, n, n, n, 4, c_box4)
     dt = time.perf_counter() - t0
-    pts = 3 * n * n * nz
     log(f"[bench] cpu baseline: {dt:.1f} s")
-    return {"value": pts / dt / 1e9, "unit": "Gpoints/s", "cores": min(threads, cores),
+    base = {"value": 3 * n ** 3 / dt / 1e9, "unit": "Gpoints/s", "cores": min(threads, cores),
             "kind": "oracle",
-            "sample": f"one sweep each of star r4, box r2, box r4 (FP64) over a {n}x{n}x{nz} "
-                      f"slab of the same input; {dt:.1f} s"}
+            "sample": f"one headline step (one FP64 sweep each of star r4, box r2, box r4) over "
+                      f"the full {n}x{n}x{n} input; {dt:.1f} s"}
+    if not check:
+        return base
+    log("[bench] errors against the oracle at every interior point")
+    kern, split, t1 = result["kernels"], result.get("split_mfma", {}), result.get("table1", {})
+    for name, shape, r, c in (("star", "star", 4, c_star), ("box2", "box", 2, c_box2),
+                              ("box4", "box", 4, c_box4)):
+        ref = I(refs.pop(name))
+        record(kern.get(name), shape, r, c, ref)
+        if name == "box4":
+            for prec in ("fp32", "bf16x3", "fp16x3s", "bf16x1"):
+                record(split.get(f"box_r4_{prec}"), "box", 4, c, ref, prec)
+        if name == "star":
+            record(t1.get("3DStarR4"), "star", 4, c, ref)
+        if name == "box2":
+            record(t1.get("3DBoxR2"), "box", 2, c, ref)
+        del ref
+    if split:
+        ref = I(oracle.box(x64, n, n, n, 3, c_box3))
+        for prec in ("fp32", "bf16x3", "fp16x3s", "bf16x1"):
+            record(split.get(f"box_r3_{prec}"), "box", 3, c_box3, ref, prec)
+        del ref
+    fns = {"star": oracle.star, "box": oracle.box, "star2d": oracle.star2d, "box2d": oracle.box2d}
+    for name, (shape, r, c, _) in table1_kernels(synth).items():
+        if name in t1 and "rel_max" not in t1[name]:
+            ref = I(fns[shape](x64, n, n, n, r, c))
+            record(t1[name], shape, r, c, ref)
+            del ref
+    for k in ("star", "box2", "box4"):
+        log(f"[bench] {k}: rel_max {kern[k]['rel_max']:.2e} rel_rms {kern[k]['rel_rms']:.2e}")
+    for k, e in split.items():
+        if isinstance(e, dict) and "rel_max" in e:
+            log(f"[bench] {k}: rel_max {e['rel_max']:.2e} rel_rms {e['rel_rms']:.2e}")
+    if "config0" in result:
+        m = 64
+        g0 = mms.Grid(m, m, m)
+        x0 = synth.uniform_grid(1, m, m, m, sy=g0.sy)
+        o0 = g0.zeros(dev)
+        mms.stencil_apply(torch.from_numpy(x0).to(dev), o0, g0, "star", 4, c_star)
+        torch.cuda.synchronize()
+        ref = oracle.star(x0.astype(np.float64), m, m, m, 4, c_star)
+        J = lambda a: a[4:4 + m, 4:4 + m, 4:4 + m]
+        result["config0"]["rel_max"], result["config0"]["rel_rms"] = errors_chunked(
+            J(o0.cpu().numpy()), J(ref))
+    return base
 
 
 # ---------------------------------------------------------------- counters

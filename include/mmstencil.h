@@ -9,13 +9,18 @@
  * gradient of a receiver misfit with respect to C2 = (v dt / h)^2.
  *
  * Conventions shared by every entry point
- *  - Grid and field pointers are DEVICE pointers owned by the caller.  The
- *    library keeps no reference after a call returns.
+ *  - Grid, field and workspace pointers are DEVICE pointers owned by the
+ *    caller.  The library keeps no reference after a call returns, allocates no
+ *    device memory and holds no mutable state other than the thread-local text
+ *    of the last HIP error: every scratch buffer a kernel needs (partial sums,
+ *    block partials, intermediate fields) is a workspace argument.
  *  - Every call is asynchronous on `stream` (a hipStream_t passed as void*,
  *    NULL = the default stream).  Errors found by the host-side checks are
  *    returned before anything is enqueued; launch failures return MMS_EHIP.
  *  - Return value 0 means success; negative values are the MMS_E* codes below.
- *    No exception crosses the ABI.  Calls on different streams are thread-safe.
+ *    No exception crosses the ABI.  Calls from different threads or on
+ *    different streams may run concurrently as long as no buffer that one of
+ *    them writes (outputs and workspaces) is read or written by another.
  *  - Grid layout (mms_grid): FP32 elements, x fastest.  Interior point (z,y,x),
  *    0 <= z < nz etc., is element (z+H)*sz + (y+H)*sy + (x+H) of the array.
  *    Requirements (MMS_EINVAL otherwise): nx, ny, nz >= 0; H >= radius and
@@ -34,14 +39,18 @@
 extern "C" {
 #endif
 
-#define MMS_ABI_VERSION 3   /* 3: mms_wave_adjoint_mu, mms_wave_scale_mu, mms_grid_aligned */
+#define MMS_ABI_VERSION 4   /* 4: caller-owned reduction workspaces, (sum, non-finite count)
+                               result pairs, mms_flat_scale_f32, mms_check_reduction;
+                               the z-chunk tuning call is gone */
 
 /* error codes */
 #define MMS_OK 0
 #define MMS_EINVAL (-1)       /* null pointer, bad layout, bad sizes, aliasing   */
 #define MMS_EUNSUPPORTED (-2) /* radius outside 1..4, unknown shape, split precision other than on a 3-D box */
 #define MMS_EHIP (-3)         /* HIP runtime or launch error (see mms_last_error)*/
-#define MMS_ENOMEM (-4)       /* a library-owned buffer could not be allocated  */
+#define MMS_ENOMEM (-4)       /* reserved: no call of this version allocates      */
+#define MMS_EUNSTABLE (-5)    /* a reduction result reports NaN or Inf values     */
+                              /* (returned by mms_check_reduction)               */
 
 /* stencil shapes (Sec. I: star = axes only, box = full (2r+1)^d cube; the 2-D
    shapes are the 2DStar / 2DBox kernels of Table I, applied to every z-plane) */
@@ -236,11 +245,11 @@ int mms_tti_step(const mms_wave *w, const mms_tti *t, int n, const float *p_prev
  * outputs (a HOST array of device pointers; entries may repeat as in mms_wave_adjoint).
  * With grad: grad += c2_scale G lam^{n+1} S(u^n) for n = max(n_lo, 1) .. n_hi, the same
  * terms as mms_wave_adjoint, formed as mu^{n+1} S(u^n) / c2; acc_block blocks as there.
- * grad is multiplied by c2 on entry and divided by it on exit (the per-step terms then
- * need no c2 operand; if a launch fails in between, MMS_EHIP is returned and grad is
- * left in the scaled units); the FP32 block partial holds mu^{n+1} S(u^n) sums, so a block
- * begun by this call must be finished by calls of this entry point (and one begun by
- * mms_wave_adjoint by that one).  Requires c2 > 0 in every interior cell
+ * The FP32 block partial holds mu^{n+1} S(u^n) sums, and the division by c2 (in FP64)
+ * happens where a sum is added to grad, so the c2 field is read once per block rather
+ * than every step.  A block begun by this call must therefore be finished by calls of
+ * this entry point (and one begun by mms_wave_adjoint by that one).  grad holds only
+ * finished terms between calls.  Requires c2 > 0 in every interior cell
  * (lam = mu / (C2 G)); results are undefined otherwise.  Buffers are checked before
  * anything is enqueued.
  */
@@ -255,28 +264,64 @@ int mms_wave_adjoint_mu(const mms_wave *w, int n_hi, int n_lo, float *const *mus
 int mms_wave_scale_mu(const mms_wave *w, const float *in, float *out, int dir, void *stream);
 
 /*
- * mms_wave_energy -- FP64 discrete energy of the leapfrog scheme without
- * sponge or source, E^{n+1/2} = sum (u^{n+1}-u^n)^2 / C2 - <u^{n+1}, S u^n>,
- * which the scheme conserves exactly for a symmetric S.  *out_dev (device) is
- * overwritten.  Cells with C2 == 0 add only the second term.
+ * FP64 reductions of FP32 data.  A fixed number of blocks strides over the data
+ * in a fixed order and writes one (partial sum, non-finite count) pair each into
+ * a caller-owned device workspace; one block then sums the pairs in a fixed tree
+ * (no atomics, so a result is bit-reproducible).  Every reduction writes a result
+ * PAIR to out_dev (device, 2 doubles, 8-byte aligned, disjoint from the
+ * workspace): out_dev[0] = the FP64 sum, out_dev[1] = the number of terms that
+ * were NaN or +-Inf, plus one if the sum itself is not finite (0 for a clean
+ * result; mms_check_reduction turns the pair into MMS_OK or MMS_EUNSTABLE).
+ * Two reductions may run at once (other streams, other threads) when their
+ * workspaces and result pairs are distinct.
  */
-int mms_wave_energy(const mms_wave *w, const float *u_n, const float *u_np1, double *out_dev,
-                    void *stream);
+#define MMS_REDUCE_WORK 2048  /* doubles of workspace for the flat and grid reductions */
 
 /*
- * FP64 reductions of FP32 data (fixed-shape two-level tree, no atomics, so a
- * result is bit-reproducible).  Results are written to *out_dev (device).
  *   mms_dot_f64:      sum over the interior of a*b (b == NULL: a*a)
  *   mms_flat_dot_f64: sum_i a[i]*b[i] over n contiguous elements (b == NULL: a*a)
  *   mms_flat_misfit_f64: 0.5 * sum_i (a[i]-b[i])^2, and resid[i] = a[i]-b[i]
- *                     when resid is non-NULL (may equal a).
- * The library keeps one small per-device buffer of partial sums for these
- * (allocated on first use; MMS_ENOMEM if that fails).
+ *                     when resid is non-NULL (may equal a)
+ * work: device, MMS_REDUCE_WORK doubles, overwritten.  MMS_EINVAL for a null
+ * input, result or workspace, a misaligned result or workspace, or a result that
+ * overlaps the workspace.
  */
-int mms_dot_f64(const float *a, const float *b, const mms_grid *g, double *out_dev, void *stream);
-int mms_flat_dot_f64(const float *a, const float *b, int64_t n, double *out_dev, void *stream);
+int mms_dot_f64(const float *a, const float *b, const mms_grid *g, double *out_dev, double *work,
+                void *stream);
+int mms_flat_dot_f64(const float *a, const float *b, int64_t n, double *out_dev, double *work,
+                     void *stream);
 int mms_flat_misfit_f64(const float *a, const float *b, float *resid, int64_t n, double *out_dev,
-                        void *stream);
+                        double *work, void *stream);
+
+/*
+ * mms_wave_energy -- FP64 discrete energy of the leapfrog scheme without
+ * sponge or source, E^{n+1/2} = sum (u^{n+1}-u^n)^2 / C2 - <u^{n+1}, S u^n>,
+ * which the scheme conserves exactly for a symmetric S, so growth of E is the
+ * signature of an unstable run (a time step beyond the CFL limit).  The result
+ * pair goes to out_dev as for the reductions above.  Cells with C2 == 0 add only
+ * the second term.  work: device workspace of at least the number of doubles
+ * that mms_wave_energy_work reports for w (it depends on the grid only).
+ */
+int mms_wave_energy_work(const mms_wave *w, int64_t *elems);
+int mms_wave_energy(const mms_wave *w, const float *u_n, const float *u_np1, double *out_dev,
+                    double *work, int64_t work_elems, void *stream);
+
+/*
+ * mms_check_reduction -- host helper: MMS_EUNSTABLE if a reduction's result pair
+ * (copied to the host) reports non-finite terms or a non-finite sum, MMS_OK
+ * otherwise, MMS_EINVAL for NULL.
+ */
+int mms_check_reduction(const double *result_host);
+
+/*
+ * mms_flat_scale_f32 -- out[i] = (float)(scale * in[i]) for i < n, with the FP64 scale
+ * read on the device from *scale_dev (so a scale that an earlier kernel produced needs
+ * no copy to the host).  This is the chain-rule step of a misfit's gradient: the
+ * residual times the upstream derivative.  out may equal in; with n = 0 nothing is read
+ * and in and out may be NULL.
+ */
+int mms_flat_scale_f32(const float *in, const double *scale_dev, float *out, int64_t n,
+                       void *stream);
 
 /*
  * mms_dense_to_grid -- out(z,y,x) = (float)(scale * in[z][y][x]) on the interior
@@ -300,9 +345,6 @@ int mms_dense_to_grid(const double *in, float *out, const mms_grid *g, double sc
  */
 int mms_grid_aligned(int64_t nx, int64_t ny, int64_t nz, int32_t halo, mms_grid *g,
                      int64_t *lead);
-
-/* Tuning of the sweep launches: z-chunk length per shape and precision (0 = automatic). */
-int mms_set_zchunk(int shape, int precision, int zchunk);
 
 const char *mms_strerror(int code);
 const char *mms_last_error(void); /* text of the last MMS_EHIP on this thread */

@@ -15,11 +15,11 @@ from dataclasses import dataclass
 import torch
 
 from . import _lib
-from ._lib import (MMS_BF16X1, MMS_BF16X3, MMS_BOX, MMS_BOX2D, MMS_FP16X3S, MMS_FP32, MMS_STAR,
-                   MMS_STAR2D, MmsError, check, lib)
+from ._lib import (MMS_BF16X1, MMS_BF16X3, MMS_BOX, MMS_BOX2D, MMS_FP16X3S, MMS_FP32,
+                   MMS_REDUCE_WORK, MMS_STAR, MMS_STAR2D, MmsError, check, lib)
 
-__all__ = ["Grid", "stencil_apply", "Wave", "Tti", "dot", "flat_dot", "flat_misfit", "dense_to_grid",
-           "set_zchunk", "MmsError", "PRECISIONS", "SHAPES"]
+__all__ = ["Grid", "stencil_apply", "Wave", "Tti", "dot", "flat_dot", "flat_misfit", "flat_scale",
+           "dense_to_grid", "reduce_work", "check_result", "MmsError", "PRECISIONS", "SHAPES"]
 
 PRECISIONS = {"fp32": MMS_FP32, "bf16x3": MMS_BF16X3, "fp16x3s": MMS_FP16X3S, "bf16x1": MMS_BF16X1}
 SHAPES = {"star": MMS_STAR, "box": MMS_BOX, "star2d": MMS_STAR2D, "box2d": MMS_BOX2D}
@@ -117,10 +117,6 @@ def stencil_apply(inp: torch.Tensor, out: torch.Tensor, grid: Grid, shape: str, 
                                  c.numel(), PRECISIONS[precision], _stream(stream))
     check(rc, "mms_stencil_apply")
     return out
-
-
-def set_zchunk(shape: str, precision: str, zchunk: int) -> None:
-    check(lib().mms_set_zchunk(SHAPES[shape], PRECISIONS[precision], int(zchunk)), "mms_set_zchunk")
 
 
 class Wave:
@@ -267,13 +263,27 @@ class Wave:
                                  _grid_ptr(q_cur, g, "q_cur"), _grid_ptr(q_next, g, "q_next"),
                                  _stream(stream)), "mms_tti_step")
 
-    def energy(self, u_n, u_np1, stream=None) -> float:
-        out = torch.zeros(1, dtype=torch.float64, device=u_n.device)
+    def energy_work(self) -> int:
+        """Doubles of workspace mms_wave_energy needs for this grid."""
+        n = ctypes.c_int64(0)
+        check(lib().mms_wave_energy_work(ctypes.byref(self._w), ctypes.byref(n)),
+              "mms_wave_energy_work")
+        return int(n.value)
+
+    def energy(self, u_n, u_np1, out=None, work=None, stream=None) -> float:
+        """Discrete energy (mms_wave_energy); raises MmsError (MMS_EUNSTABLE) if it meets
+        NaN or Inf.  `out` (2 FP64 on the device) receives the result pair."""
+        if out is None:
+            out = torch.zeros(2, dtype=torch.float64, device=u_n.device)
+        need = self.energy_work()
+        if work is None:
+            work = torch.empty(max(need, 1), dtype=torch.float64, device=u_n.device)
         check(lib().mms_wave_energy(ctypes.byref(self._w), _grid_ptr(u_n, self.grid, "u_n"),
                                     _grid_ptr(u_np1, self.grid, "u_np1"),
-                                    _dev_ptr(out, "out", torch.float64), _stream(stream)),
-              "mms_wave_energy")
-        return float(out.item())
+                                    _dev_ptr(out, "out", torch.float64, 2),
+                                    _dev_ptr(work, "work", torch.float64, need), work.numel(),
+                                    _stream(stream)), "mms_wave_energy")
+        return check_result(out, "mms_wave_energy")
 
 
 class Tti:
@@ -291,35 +301,77 @@ class Tti:
                               ctypes.c_void_p(self.work.data_ptr()))
 
 
-def dot(a: torch.Tensor, b: torch.Tensor | None, grid: Grid, stream=None) -> float:
-    out = torch.zeros(1, dtype=torch.float64, device=a.device)
+def reduce_work(device) -> torch.Tensor:
+    """A workspace for one FP64 reduction (MMS_REDUCE_WORK doubles).  Taken from torch's
+    stream-ordered caching allocator, so a fresh one per call costs no device allocation."""
+    return torch.empty(MMS_REDUCE_WORK, dtype=torch.float64, device=device)
+
+
+def check_result(pair: torch.Tensor, where: str = "reduction") -> float:
+    """Copy a reduction's (sum, non-finite count) pair to the host; raise MmsError
+    (MMS_EUNSTABLE) if it reports NaN or Inf, else return the sum."""
+    host = pair.detach().to("cpu", torch.float64).contiguous()
+    check(lib().mms_check_reduction(ctypes.cast(host.data_ptr(), ctypes.POINTER(ctypes.c_double))),
+          where)
+    return float(host[0])
+
+
+def _pair(out, device):
+    if out is None:
+        return torch.zeros(2, dtype=torch.float64, device=device)
+    return out
+
+
+def dot(a: torch.Tensor, b: torch.Tensor | None, grid: Grid, out=None, work=None,
+        stream=None) -> float:
+    """FP64 interior dot product (mms_dot_f64); raises MmsError on NaN or Inf."""
+    out = _pair(out, a.device)
+    work = reduce_work(a.device) if work is None else work
     g = grid.c()
     check(lib().mms_dot_f64(_grid_ptr(a, grid, "a"), _grid_ptr(b, grid, "b"), ctypes.byref(g),
-                            _dev_ptr(out, "out", torch.float64), _stream(stream)), "mms_dot_f64")
-    return float(out.item())
+                            _dev_ptr(out, "out", torch.float64, 2),
+                            _dev_ptr(work, "work", torch.float64, MMS_REDUCE_WORK),
+                            _stream(stream)), "mms_dot_f64")
+    return check_result(out, "mms_dot_f64")
 
 
-def flat_dot(a: torch.Tensor, b: torch.Tensor | None = None, stream=None) -> float:
-    out = torch.zeros(1, dtype=torch.float64, device=a.device)
+def flat_dot(a: torch.Tensor, b: torch.Tensor | None = None, out=None, work=None,
+             stream=None) -> float:
+    """FP64 dot product of two flat FP32 tensors (mms_flat_dot_f64); raises on NaN or Inf."""
+    out = _pair(out, a.device)
+    work = reduce_work(a.device) if work is None else work
     n = a.numel()
     check(lib().mms_flat_dot_f64(_dev_ptr(a, "a", torch.float32), _dev_ptr(b, "b", torch.float32, n),
-                                 n, _dev_ptr(out, "out", torch.float64), _stream(stream)),
-          "mms_flat_dot_f64")
-    return float(out.item())
+                                 n, _dev_ptr(out, "out", torch.float64, 2),
+                                 _dev_ptr(work, "work", torch.float64, MMS_REDUCE_WORK),
+                                 _stream(stream)), "mms_flat_dot_f64")
+    return check_result(out, "mms_flat_dot_f64")
 
 
 def flat_misfit(a: torch.Tensor, b: torch.Tensor, resid: torch.Tensor | None = None,
-                out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """0.5 * sum (a - b)^2 in FP64 on the device (returned as a 1-element tensor);
-    writes resid = a - b when given."""
-    if out is None:
-        out = torch.zeros(1, dtype=torch.float64, device=a.device)
+                out: torch.Tensor | None = None, work=None, stream=None) -> torch.Tensor:
+    """0.5 * sum (a - b)^2 in FP64 on the device, returned as the device result pair
+    (sum, non-finite count) without a host synchronisation; writes resid = a - b when
+    given."""
+    out = _pair(out, a.device)
+    work = reduce_work(a.device) if work is None else work
     n = a.numel()
     check(lib().mms_flat_misfit_f64(_dev_ptr(a, "a", torch.float32),
                                     _dev_ptr(b, "b", torch.float32, n),
                                     _dev_ptr(resid, "resid", torch.float32, n), n,
-                                    _dev_ptr(out, "out", torch.float64), _stream(stream)),
-          "mms_flat_misfit_f64")
+                                    _dev_ptr(out, "out", torch.float64, 2),
+                                    _dev_ptr(work, "work", torch.float64, MMS_REDUCE_WORK),
+                                    _stream(stream)), "mms_flat_misfit_f64")
+    return out
+
+
+def flat_scale(inp: torch.Tensor, scale: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+    """out = (float)(scale * inp) with the FP64 scale read on the device (mms_flat_scale_f32)."""
+    n = inp.numel()
+    check(lib().mms_flat_scale_f32(_dev_ptr(inp, "inp", torch.float32),
+                                   _dev_ptr(scale, "scale", torch.float64, 1),
+                                   _dev_ptr(out, "out", torch.float32, n), n, _stream(stream)),
+          "mms_flat_scale_f32")
     return out
 
 

@@ -6,15 +6,17 @@ import os
 
 from ._build import LIB
 
-MMS_OK, MMS_EINVAL, MMS_EUNSUPPORTED, MMS_EHIP, MMS_ENOMEM = 0, -1, -2, -3, -4
+MMS_OK, MMS_EINVAL, MMS_EUNSUPPORTED, MMS_EHIP, MMS_ENOMEM, MMS_EUNSTABLE = 0, -1, -2, -3, -4, -5
+MMS_REDUCE_WORK = 2048
 MMS_STAR, MMS_BOX, MMS_STAR2D, MMS_BOX2D = 0, 1, 2, 3
 MMS_FP32, MMS_BF16X3, MMS_FP16X3S, MMS_BF16X1 = 0, 1, 2, 3
 
 EXPORTS = ("mms_stencil_apply", "mms_wave_step", "mms_wave_record", "mms_wave_forward",
            "mms_wave_adjoint_step", "mms_wave_adjoint", "mms_wave_adjoint_mu", "mms_wave_scale_mu",
            "mms_wave_energy", "mms_dot_f64",
-           "mms_flat_dot_f64", "mms_flat_misfit_f64", "mms_dense_to_grid", "mms_grid_aligned", "mms_set_zchunk",
-           "mms_strerror", "mms_last_error", "mms_abi_version", "mms_vti_step", "mms_tti_step")
+           "mms_flat_dot_f64", "mms_flat_misfit_f64", "mms_dense_to_grid", "mms_grid_aligned",
+           "mms_strerror", "mms_last_error", "mms_abi_version", "mms_vti_step", "mms_tti_step",
+           "mms_wave_energy_work", "mms_flat_scale_f32", "mms_check_reduction")
 
 
 class MmsGrid(ctypes.Structure):
@@ -71,14 +73,16 @@ def lib():
                                           vp, vp, vp]
         L.mms_wave_scale_mu.argtypes = [wp, vp, vp, i32, vp]
         L.mms_grid_aligned.argtypes = [i64, i64, i64, ctypes.c_int32, gp, ctypes.POINTER(i64)]
-        L.mms_wave_energy.argtypes = [wp, vp, vp, vp, vp]
+        L.mms_wave_energy_work.argtypes = [wp, ctypes.POINTER(i64)]
+        L.mms_wave_energy.argtypes = [wp, vp, vp, vp, vp, i64, vp]
         L.mms_vti_step.argtypes = [wp, i32] + [vp] * 8 + [vp]
         L.mms_tti_step.argtypes = [wp, ctypes.POINTER(MmsTti), i32] + [vp] * 6 + [vp]
-        L.mms_dot_f64.argtypes = [vp, vp, gp, vp, vp]
-        L.mms_flat_dot_f64.argtypes = [vp, vp, i64, vp, vp]
-        L.mms_flat_misfit_f64.argtypes = [vp, vp, vp, i64, vp, vp]
+        L.mms_dot_f64.argtypes = [vp, vp, gp, vp, vp, vp]
+        L.mms_flat_dot_f64.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.mms_flat_misfit_f64.argtypes = [vp, vp, vp, i64, vp, vp, vp]
+        L.mms_flat_scale_f32.argtypes = [vp, vp, vp, i64, vp]
+        L.mms_check_reduction.argtypes = [ctypes.POINTER(ctypes.c_double)]
         L.mms_dense_to_grid.argtypes = [vp, vp, gp, ctypes.c_double, vp]
-        L.mms_set_zchunk.argtypes = [i32, i32, i32]
         L.mms_strerror.argtypes = [i32]
         L.mms_strerror.restype = ctypes.c_char_p
         L.mms_last_error.restype = ctypes.c_char_p

@@ -20,7 +20,8 @@ for 256^3 x 1000 steps, within one MI355X's 288 GB) and the backward pass
 runs the adjoint over all steps in one call with no recompute.
 
 Misfit.apply(traces, d_obs) -> J = 0.5 sum (d - d_obs)^2 (FP64, one element),
-computed and differentiated by the library's reduction kernel.
+computed by the library's reduction kernel; its backward scales the residual by
+the upstream derivative in the library (mms_flat_scale_f32), with no host sync.
 """
 from __future__ import annotations
 
@@ -28,7 +29,7 @@ from dataclasses import dataclass, field
 
 import torch
 
-from . import Grid, Wave, dense_to_grid, flat_misfit
+from . import Grid, Wave, dense_to_grid, flat_misfit, flat_scale
 
 
 @dataclass
@@ -154,14 +155,16 @@ class Misfit(torch.autograd.Function):
     def forward(ctx, traces, d_obs):
         t = traces.detach().contiguous()
         resid = torch.empty_like(t)
-        J = flat_misfit(t, d_obs.detach().contiguous(), resid=resid)
+        pair = flat_misfit(t, d_obs.detach().contiguous(), resid=resid)
         ctx.save_for_backward(resid)
-        return J
+        return pair[:1].clone()    # J; pair[1] counts non-finite terms
 
     @staticmethod
     def backward(ctx, gJ):
         (resid,) = ctx.saved_tensors
-        return resid * gJ.to(resid.dtype), None
+        # dJ/dd = resid times the upstream derivative, read on the device by the library
+        scale = gJ.detach().to(torch.float64).reshape(1).contiguous()
+        return flat_scale(resid, scale, torch.empty_like(resid)), None
 
 
 def propagate(m, u0, u1, prob: Problem):

@@ -1,10 +1,9 @@
 // C ABI of libmmstencil: argument checks, dispatch and error reporting.
 // Every check runs on the host before any HIP call, so it is testable without
 // a GPU.
+#include <math.h>
 #include <stdio.h>
 #include <string.h>
-
-#include <mutex>
 
 #include "mms_internal.h"
 
@@ -17,9 +16,8 @@ int wave_record(const mms_wave *w, int n, const float *u, hipStream_t s);
 int wave_adjoint_mu_step(const mms_wave *w, int n, const float *m2, const float *m1, float *m0,
                          const float *resid, const float *un, double *grad, hipStream_t s);
 int wave_scale_mu(const mms_wave *w, const float *in, float *out, int dir, hipStream_t s);
-int wave_grad_c2(const mms_wave *w, double *grad, int dir, hipStream_t s);
 int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *out, double *partials,
-                int64_t npartials, hipStream_t s);
+                hipStream_t s);
 int64_t wave_energy_blocks(const mms_wave *w);
 int dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, hipStream_t s);
 int tti_step(const mms_wave *w, const mms_tti *t, int n, const float *pp, const float *pc,
@@ -31,36 +29,10 @@ int reduce_grid_dot(const float *a, const float *b, const mms_grid *g, double *o
                     hipStream_t s);
 int reduce_flat(const float *a, const float *b, float *resid, int64_t n, int misfit, double *out,
                 double *part, hipStream_t s);
-int reduce_partials_count();
+int flat_scale(const float *in, const double *scale, float *out, int64_t n, hipStream_t s);
 
 namespace {
 thread_local char g_last[256] = "";
-int g_zchunk[4][4] = {};
-
-// per-device buffer of FP64 partial sums used by the reductions
-constexpr int kMaxDev = 64;
-constexpr int64_t kPartials = 1 << 16;
-double *g_partials[kMaxDev] = {};
-std::mutex g_mu;
-
-int partials(double **p) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev < 0 || dev >= kMaxDev) return MMS_EINVAL;
-    std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_partials[dev]) {
-        e = hipMalloc((void **)&g_partials[dev], kPartials * sizeof(double));
-        if (e != hipSuccess) {
-            g_partials[dev] = nullptr;
-            snprintf(g_last, sizeof g_last, "hipMalloc of the partial-sum buffer: %s",
-                     hipGetErrorString(e));
-            return MMS_ENOMEM;
-        }
-    }
-    *p = g_partials[dev];
-    return MMS_OK;
-}
 }  // namespace
 
 int hip_fail(hipError_t e, const char *where) {
@@ -89,16 +61,18 @@ bool overlap(const void *a, int64_t abytes, const void *b, int64_t bbytes) {
     return pa < pb + bbytes && pb < pa + abytes;
 }
 
-int zchunk_override(int shape, int precision) {
-    if (shape < 0 || shape > 3 || precision < 0 || precision > 3) return 0;
-    return g_zchunk[shape][precision];
-}
-
 }  // namespace mms
 
 using namespace mms;
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+static bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+// A reduction's result pair and its workspace: both present, 8-byte aligned, disjoint.
+static bool reduce_buffers_ok(const double *out, const double *work, int64_t work_elems) {
+    if (!out || !work || !aligned8(out) || !aligned8(work)) return false;
+    return !overlap(out, 2 * (int64_t)sizeof(double), work, work_elems * (int64_t)sizeof(double));
+}
 
 extern "C" {
 
@@ -111,6 +85,7 @@ const char *mms_strerror(int code) {
         case MMS_EUNSUPPORTED: return "unsupported radius, shape or precision";
         case MMS_EHIP: return "HIP runtime error";
         case MMS_ENOMEM: return "out of device memory";
+        case MMS_EUNSTABLE: return "non-finite values (NaN or Inf) in a reduction";
         default: return "unknown error";
     }
 }
@@ -130,12 +105,6 @@ int mms_grid_aligned(int64_t nx, int64_t ny, int64_t nz, int32_t halo, mms_grid 
     g->sy = (need + 31) & ~(int64_t)31;
     g->sz = g->sy * (ny + 2 * (int64_t)halo);
     *lead = (32 - halo % 32) % 32;
-    return MMS_OK;
-}
-
-int mms_set_zchunk(int shape, int precision, int zchunk) {
-    if (shape < 0 || shape > 3 || precision < 0 || precision > 3 || zchunk < 0) return MMS_EINVAL;
-    g_zchunk[shape][precision] = zchunk;
     return MMS_OK;
 }
 
@@ -321,10 +290,6 @@ int mms_wave_adjoint_mu(const mms_wave *w, int n_hi, int n_lo, float *const *mus
     }
     if (grid_empty(&w->g)) return MMS_OK;
     hipStream_t s = (hipStream_t)stream;
-    // the gradient is accumulated as sum mu^{n+1} S(u^n) and divided by c2 once: the
-    // caller's grad is brought to that scale first and back at the end
-    if (grad)
-        if (int rc = wave_grad_c2(w, grad, +1, s)) return rc;
     for (int n = n_hi; n >= n_lo; --n) {
         const int i = n - n_lo;
         const float *un = (grad && n >= 1) ? us[i] : nullptr;
@@ -332,7 +297,6 @@ int mms_wave_adjoint_mu(const mms_wave *w, int n_hi, int n_lo, float *const *mus
                                       n >= 1 ? grad : nullptr, s);
         if (rc) return rc;
     }
-    if (grad) return wave_grad_c2(w, grad, -1, s);
     return MMS_OK;
 }
 
@@ -345,18 +309,24 @@ int mms_wave_scale_mu(const mms_wave *w, const float *in, float *out, int dir, v
     return wave_scale_mu(w, in, out, dir, (hipStream_t)stream);
 }
 
-int mms_wave_energy(const mms_wave *w, const float *u_n, const float *u_np1, double *out_dev,
-                    void *stream) {
+int mms_wave_energy_work(const mms_wave *w, int64_t *elems) {
     if (int rc = wave_ok(w)) return rc;
-    if (!u_n || !u_np1 || !out_dev) return MMS_EINVAL;
-    double *part = nullptr;
-    if (int rc = partials(&part)) return rc;
-    if (wave_energy_blocks(w) > kPartials) return MMS_EINVAL;
-    if (grid_empty(&w->g)) {
-        hipError_t e = hipMemsetAsync(out_dev, 0, sizeof(double), (hipStream_t)stream);
-        return e == hipSuccess ? MMS_OK : hip_fail(e, "hipMemsetAsync");
-    }
-    return wave_energy(w, u_n, u_np1, out_dev, part, kPartials, (hipStream_t)stream);
+    if (!elems) return MMS_EINVAL;
+    *elems = grid_empty(&w->g) ? 0 : 2 * wave_energy_blocks(w);
+    return MMS_OK;
+}
+
+int mms_wave_energy(const mms_wave *w, const float *u_n, const float *u_np1, double *out_dev,
+                    double *work, int64_t work_elems, void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!u_n || !u_np1) return MMS_EINVAL;
+    int64_t need = 0;
+    if (int rc = mms_wave_energy_work(w, &need)) return rc;
+    if (work_elems < need || need > (int64_t)0x7fffffff) return MMS_EINVAL;
+    if (!out_dev || !aligned8(out_dev) || (need > 0 && !reduce_buffers_ok(out_dev, work, need)))
+        return MMS_EINVAL;
+    if (grid_empty(&w->g)) return fill_pair(out_dev, 0.0, (hipStream_t)stream);
+    return wave_energy(w, u_n, u_np1, out_dev, work, (hipStream_t)stream);
 }
 
 int mms_dense_to_grid(const double *in, float *out, const mms_grid *g, double scale, void *stream) {
@@ -366,26 +336,41 @@ int mms_dense_to_grid(const double *in, float *out, const mms_grid *g, double sc
     return dense_to_grid(in, out, g, scale, (hipStream_t)stream);
 }
 
-int mms_dot_f64(const float *a, const float *b, const mms_grid *g, double *out_dev, void *stream) {
-    if (!a || !out_dev || !grid_ok(g, 1)) return MMS_EINVAL;
-    double *part = nullptr;
-    if (int rc = partials(&part)) return rc;
-    return reduce_grid_dot(a, b, g, out_dev, part, (hipStream_t)stream);
+int mms_dot_f64(const float *a, const float *b, const mms_grid *g, double *out_dev, double *work,
+                void *stream) {
+    if (!a || !grid_ok(g, 1)) return MMS_EINVAL;
+    if (!reduce_buffers_ok(out_dev, work, MMS_REDUCE_WORK)) return MMS_EINVAL;
+    return reduce_grid_dot(a, b, g, out_dev, work, (hipStream_t)stream);
 }
 
-int mms_flat_dot_f64(const float *a, const float *b, int64_t n, double *out_dev, void *stream) {
-    if (!a || !out_dev || n < 0) return MMS_EINVAL;
-    double *part = nullptr;
-    if (int rc = partials(&part)) return rc;
-    return reduce_flat(a, b, nullptr, n, 0, out_dev, part, (hipStream_t)stream);
+int mms_flat_dot_f64(const float *a, const float *b, int64_t n, double *out_dev, double *work,
+                     void *stream) {
+    if (!a || n < 0) return MMS_EINVAL;
+    if (!reduce_buffers_ok(out_dev, work, MMS_REDUCE_WORK)) return MMS_EINVAL;
+    return reduce_flat(a, b, nullptr, n, 0, out_dev, work, (hipStream_t)stream);
 }
 
 int mms_flat_misfit_f64(const float *a, const float *b, float *resid, int64_t n, double *out_dev,
-                        void *stream) {
-    if (!a || !b || !out_dev || n < 0) return MMS_EINVAL;
-    double *part = nullptr;
-    if (int rc = partials(&part)) return rc;
-    return reduce_flat(a, b, resid, n, 1, out_dev, part, (hipStream_t)stream);
+                        double *work, void *stream) {
+    if (!a || !b || n < 0) return MMS_EINVAL;
+    if (!reduce_buffers_ok(out_dev, work, MMS_REDUCE_WORK)) return MMS_EINVAL;
+    return reduce_flat(a, b, resid, n, 1, out_dev, work, (hipStream_t)stream);
+}
+
+int mms_flat_scale_f32(const float *in, const double *scale_dev, float *out, int64_t n,
+                       void *stream) {
+    if (!scale_dev || n < 0 || !aligned8(scale_dev)) return MMS_EINVAL;
+    if (n == 0) return MMS_OK;
+    if (!in || !out) return MMS_EINVAL;
+    const int64_t bytes = n * (int64_t)sizeof(float);
+    if (in != out && overlap(in, bytes, out, bytes)) return MMS_EINVAL;
+    return flat_scale(in, scale_dev, out, n, (hipStream_t)stream);
+}
+
+int mms_check_reduction(const double *result) {
+    if (!result) return MMS_EINVAL;
+    if (result[1] != 0.0 || !isfinite(result[0])) return MMS_EUNSTABLE;
+    return MMS_OK;
 }
 
 }  // extern "C"

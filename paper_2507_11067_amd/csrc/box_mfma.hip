@@ -351,13 +351,10 @@ int launch_rp(const float *in, float *out, const mms_grid *gd, const float *coef
     g.sz = gd->sz;
     g.ntx = (g.nx + BXT - 1) / BXT;
     g.nty = (g.ny + BYT - 1) / BYT;
-    int zc = zchunk_override(MMS_BOX, PREC);
-    if (zc <= 0) {
-        // one block per CU: about 256 blocks, chunks of at most 128 planes
-        const int64_t cols = (int64_t)g.ntx * g.nty;
-        zc = (int)((int64_t)g.nz * cols / 256);
-        zc = zc < 32 ? 32 : (zc > 128 ? 128 : zc);
-    }
+    // one block per CU: about 256 blocks, chunks of at most 128 planes
+    const int64_t cols = (int64_t)g.ntx * g.nty;
+    int zc = (int)((int64_t)g.nz * cols / 256);
+    zc = zc < 32 ? 32 : (zc > 128 ? 128 : zc);
     g.zchunk = zc;
     g.nzc = (g.nz + zc - 1) / zc;
     float cmax = 0.f;

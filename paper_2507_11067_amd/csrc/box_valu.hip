@@ -220,15 +220,12 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     g.sz = gd->sz;
     g.ntx = (g.nx + 4 * TX - 1) / (4 * TX);
     g.nty = (g.ny + TY - 1) / TY;
-    int zc = zchunk_override(MMS_BOX, MMS_FP32);
-    if (zc <= 0) {
-        const int64_t cols = (int64_t)g.ntx * g.nty;
-        zc = (int)((int64_t)g.nz * cols / 4096);
-        zc = zc < 16 ? 16 : zc;
-        // radius 1 is bound by HBM: long chunks cut the re-read halo planes
-        // (measured at 512^3: 512 Gpoints/s at 128 planes against 441 at 32)
-        if (R == 1) zc = 128;
-    }
+    const int64_t cols = (int64_t)g.ntx * g.nty;
+    int zc = (int)((int64_t)g.nz * cols / 4096);
+    zc = zc < 16 ? 16 : zc;
+    // radius 1 is bound by HBM: long chunks cut the re-read halo planes
+    // (measured at 512^3: 512 Gpoints/s at 128 planes against 441 at 32)
+    if (R == 1) zc = 128;
     g.zchunk = zc;
     g.nzc = (g.nz + zc - 1) / zc;
     for (int i = 0; i < W * W * W; ++i) a.c[i] = coeffs[i];

@@ -45,7 +45,11 @@ inline int balanced_tile_words(int nx, int lanes, int *ntx) {
     return w < 1 ? 1 : w;
 }
 
-int zchunk_override(int shape, int precision);
+// FP64 reduction tail shared by the reductions: out[0] = sum of n partial sums,
+// out[1] = sum of n counts of non-finite terms (+1 if the sum itself is not finite);
+// part holds n (sum, count) pairs.  fill_pair writes (v, 0).
+int finish_pairs(const double *part, int n, double *out, hipStream_t s);
+int fill_pair(double *out, double v, hipStream_t s);
 
 // z-chunk length so that (x, y) tiles times z chunks fill `slots` concurrent
 // blocks in one wave (slots = CUs x blocks per CU), clamped to [zmin, zmax].

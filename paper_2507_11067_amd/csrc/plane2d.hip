@@ -229,13 +229,10 @@ int launch_plane_r(const float *in, float *out, const mms_grid *gd, const float 
     g.sz = gd->sz;
     g.ntx = (g.nx + 4 * PTX - 1) / (4 * PTX);
     g.nty = (g.ny + PTY * PNY - 1) / (PTY * PNY);
-    int zc = zchunk_override(SHAPE == SH_STAR2D ? MMS_STAR2D : MMS_BOX2D, MMS_FP32);
-    if (zc <= 0) {
-        // planes are independent, so the only per-block overhead is the first
-        // plane's load
-        zc = pick_zchunk_rounds(g.nz, (int64_t)g.ntx * g.nty, launch_slots(kern, PTX * PTY), 1,
-                                128, 1);
-    }
+    // planes are independent, so the only per-block overhead is the first
+    // plane's load
+    const int zc = pick_zchunk_rounds(g.nz, (int64_t)g.ntx * g.nty,
+                                      launch_slots(kern, PTX * PTY), 1, 128, 1);
     g.zchunk = zc;
     g.nzc = (g.nz + zc - 1) / zc;
     const int n = SHAPE == SH_STAR2D ? 2 * (2 * R + 1) : (2 * R + 1) * (2 * R + 1);

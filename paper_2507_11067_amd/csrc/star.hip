@@ -219,12 +219,9 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     g.sz = gd->sz;
     g.txa = balanced_tile_words(g.nx, TX, &g.ntx);
     g.nty = (g.ny + TY - 1) / TY;
-    int zc = zchunk_override(MMS_STAR, MMS_FP32);
-    if (zc <= 0) {
-        // one block per CU (the LDS ring fills most of a CU's LDS): enough z chunks
-        // to give every CU one block, chunks of 8 to 128 planes
-        zc = pick_zchunk(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128);
-    }
+    // one block per CU (the LDS ring fills most of a CU's LDS): enough z chunks
+    // to give every CU one block, chunks of 8 to 128 planes
+    const int zc = pick_zchunk(g.nz, (int64_t)g.ntx * g.nty, 256, 8, 128);
     g.zchunk = zc;
     g.nzc = (g.nz + zc - 1) / zc;
     for (int a_ = 0; a_ < 3; ++a_)

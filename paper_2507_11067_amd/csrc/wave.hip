@@ -45,7 +45,7 @@ struct WaveArgs {
     float *part;          // FP32 partial of the current block (image or grad), or NULL
     int part_first;       // with part: first step of a block (part = term)
     int part_last;        // with part: last step of a block (acc64 += part + term)
-    double *partials;     // ENERGY: one FP64 partial per block
+    double *partials;     // ENERGY: one (FP64 partial, non-finite count) pair per block
     const float *src;     // device pointer to dt^2 f^n, or NULL
     int src_z, src_y, src_x;
     int sponge_w;
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     constexpr int NHK = (NH + NT - 1) / NT;
     constexpr int NR = R + 2;   // LDS ring: planes z .. z+R+1
     __shared__ float4 ring[NR][LH][LW4];
-    __shared__ double sred[NT / 64];
+    __shared__ double sred[2 * (NT / 64)];
 
     const Geom &g = a.g;
     int b = mms_xcd_remap(blockIdx.x, gridDim.x);
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
 
     const float *c = a.c;
     const float srcv = (MODE == MODE_FWD && a.src) ? *a.src : 0.f;
-    double esum = 0.0;
+    double esum = 0.0, ebad = 0.0;
     for (int z = zb; z < ze;) {
 #pragma unroll
         for (int ph = 0; ph < Q; ++ph) {
@@ -288,6 +288,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                             double t = -(double)p0v[e] * (double)o[e];
                             if (p1v[e] != 0.f) t += d * d / ((double)a.c2s * (double)p1v[e]);
                             esum += t;
+                            ebad += isfinite(t) ? 0.0 : 1.0;
                         }
                     }
                 }
@@ -317,10 +318,21 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
                             t[e] = MODE == MODE_FWD ? r[e] * r[e]
-                                   : a.mu_form ? p0v[e] * o[e]      // mu^{n+1} S(u^n), / c2 later
+                                   : a.mu_form ? p0v[e] * o[e]      // mu^{n+1} S(u^n), / c2 below
                                                : a.c2s * gz * gown[e] * p0v[e] * o[e];
+                        // mu form: c2 G lam^{n+1} S(u^n) = mu^{n+1} S(u^n) / c2, with c2 the field
+                        // (C2 = c2s c2); the division is done in FP64 where a sum reaches acc64,
+                        // so the c2 field is read once per block of steps, not every step
+                        double rc2[4] = {1.0, 1.0, 1.0, 1.0};
+                        if (MODE == MODE_GRAD && a.mu_form && (!a.part || a.part_last)) {
+                            const float4 cf = ld(a.c2, z, own_off, own_ok);
+                            rc2[0] = 1.0 / (double)cf.x;
+                            rc2[1] = 1.0 / (double)cf.y;
+                            rc2[2] = 1.0 / (double)cf.z;
+                            rc2[3] = 1.0 / (double)cf.w;
+                        }
                         auto t64 = [&](int e) -> double {
-                            return MODE == MODE_FWD ? (double)r[e] * (double)r[e] : (double)t[e];
+                            return MODE == MODE_FWD ? (double)r[e] * (double)r[e] : (double)t[e] * rc2[e];
                         };
                         double *pa = a.acc64 + dense;
                         // four cells in range on a 16-byte aligned dense row: one 16-byte
@@ -356,10 +368,10 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                                 if (a.part_last) {
                                     double2 *p2 = reinterpret_cast<double2 *>(pa);
                                     double2 lo = p2[0], hi = p2[1];
-                                    lo.x += (double)sum[0];
-                                    lo.y += (double)sum[1];
-                                    hi.x += (double)sum[2];
-                                    hi.y += (double)sum[3];
+                                    lo.x += (double)sum[0] * rc2[0];
+                                    lo.y += (double)sum[1] * rc2[1];
+                                    hi.x += (double)sum[2] * rc2[2];
+                                    hi.y += (double)sum[3] * rc2[3];
                                     p2[0] = lo;
                                     p2[1] = hi;
                                 } else {
@@ -371,7 +383,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                                     if (x0 + e < g.nx) {
                                         const float sum = a.part_first ? t[e] : pp[e] + t[e];
                                         if (a.part_last)
-                                            pa[e] += (double)sum;
+                                            pa[e] += (double)sum * rc2[e];
                                         else
                                             pp[e] = sum;
                                     }
@@ -393,14 +405,24 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
     }
     if constexpr (MODE == MODE_ENERGY) {
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) esum += __shfl_xor(esum, o);
-        if ((tid & 63) == 0) sred[tid >> 6] = esum;
+        for (int o = 32; o > 0; o >>= 1) {
+            esum += __shfl_xor(esum, o);
+            ebad += __shfl_xor(ebad, o);
+        }
+        if ((tid & 63) == 0) {
+            sred[2 * (tid >> 6)] = esum;
+            sred[2 * (tid >> 6) + 1] = ebad;
+        }
         __syncthreads();
         if (tid == 0) {
-            double s = 0.0;
+            double s = 0.0, bad = 0.0;
 #pragma unroll
-            for (int w = 0; w < NT / 64; ++w) s += sred[w];
-            a.partials[blockIdx.x] = s;
+            for (int w = 0; w < NT / 64; ++w) {
+                s += sred[2 * w];
+                bad += sred[2 * w + 1];
+            }
+            a.partials[2 * blockIdx.x] = s;
+            a.partials[2 * blockIdx.x + 1] = bad;
         }
     }
 }
@@ -445,19 +467,6 @@ __global__ void scale_mu_kernel(WaveArgs a, const float *in, float *out, int dir
     out[off] = dir > 0 ? in[off] * f : in[off] / f;
 }
 
-// dense FP64 grad times (dir > 0) or over (dir < 0) the c2 field
-__global__ void grad_c2_kernel(WaveArgs a, double *grad, int dir) {
-    const Geom &g = a.g;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t np = (int64_t)g.nx * g.ny * g.nz;
-    if (i >= np) return;
-    const int x = (int)(i % g.nx);
-    const int y = (int)((i / g.nx) % g.ny);
-    const int z = (int)(i / ((int64_t)g.nx * g.ny));
-    const double c = (double)a.c2[(int64_t)z * g.sz + (int64_t)y * g.sy + x];
-    grad[i] = dir > 0 ? grad[i] * c : grad[i] / c;
-}
-
 __global__ void dense_to_grid_kernel(const double *in, float *out, int nx, int ny, int64_t sy,
                                      int64_t sz, double scale) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -470,19 +479,6 @@ __global__ void record_kernel(const float *u0, float *tr, int nx, int ny, int64_
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x < nx) tr[(int64_t)y * nx + x] = u0[(int64_t)y * sy + x];
-}
-
-__global__ void sum_partials_kernel(const double *p, int n, double *out) {
-    __shared__ double s[256];
-    double v = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) v += p[i];
-    s[threadIdx.x] = v;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = s[0];
 }
 
 // Tile shape: up to 256 x 16 cells per block (64 x 16 lanes); the LDS ring fills most
@@ -607,7 +603,7 @@ int wave_adjoint_mu_step(const mms_wave *w, int n, const float *m2, const float 
     a.f0 = m1 + o;
     const int rc = launch_mode<MODE_ADJMU>(a, &w->g, w->radius, s);
     if (rc || !grad) return rc;
-    // gradient terms mu^{n+1} S(u^n) (the division by c2 happens once per call)
+    // gradient terms mu^{n+1} S(u^n) / c2 (the division where a sum reaches grad)
     WaveArgs b = base_args(w);
     b.f0 = un + o;
     b.p0 = m1 + o;
@@ -632,15 +628,6 @@ int wave_scale_mu(const mms_wave *w, const float *in, float *out, int dir, hipSt
     return check_launch("scale_mu_kernel");
 }
 
-int wave_grad_c2(const mms_wave *w, double *grad, int dir, hipStream_t s) {
-    WaveArgs a = base_args(w);
-    fill_geom(a.g, &w->g);
-    const int64_t np = w->g.nx * w->g.ny * w->g.nz;
-    hipLaunchKernelGGL(grad_c2_kernel, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, a, grad,
-                       dir);
-    return check_launch("grad_c2_kernel");
-}
-
 int wave_record(const mms_wave *w, int n, const float *u, hipStream_t s) {
     const int64_t o = (int64_t)w->g.halo * (w->g.sz + w->g.sy + 1);
     const dim3 grid((unsigned)((w->g.nx + 255) / 256), (unsigned)w->g.ny);
@@ -659,7 +646,7 @@ int dense_to_grid(const double *in, float *out, const mms_grid *g, double scale,
 }
 
 int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *out, double *partials,
-                int64_t npartials, hipStream_t s) {
+                hipStream_t s) {
     WaveArgs a = base_args(w);
     const int64_t o = (int64_t)w->g.halo * (w->g.sz + w->g.sy + 1);
     a.f0 = un + o;
@@ -667,11 +654,9 @@ int wave_energy(const mms_wave *w, const float *un, const float *unp1, double *o
     a.partials = partials;
     fill_geom(a.g, &w->g);
     const int64_t nblk = (int64_t)a.g.ntx * a.g.nty * a.g.nzc;
-    if (nblk > npartials) return MMS_ENOMEM;
     int rc = launch_mode<MODE_ENERGY>(a, &w->g, w->radius, s);
     if (rc) return rc;
-    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, partials, (int)nblk, out);
-    return check_launch("sum_partials_kernel");
+    return finish_pairs(partials, (int)nblk, out, s);
 }
 
 int64_t wave_energy_blocks(const mms_wave *w) {

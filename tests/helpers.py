@@ -24,3 +24,19 @@ def halo_is_zero(a, grid):
     m = np.ones(a.shape, dtype=bool)
     m[H:H + grid.nz, H:H + grid.ny, H:H + grid.nx] = False
     return not np.any(a[m])
+
+
+def rel_errors_chunked(got: np.ndarray, ref: np.ndarray, chunk: int = 32):
+    """rel_errors of two equally shaped [z][y][x] arrays, accumulated over chunks of z planes
+    in FP64 (for full 512^3 grids: no whole-grid FP64 temporaries)."""
+    assert got.shape == ref.shape
+    dmax = rmax = dss = rss = 0.0
+    for z0 in range(0, got.shape[0], chunk):
+        g = np.asarray(got[z0:z0 + chunk], dtype=np.float64)
+        r = np.asarray(ref[z0:z0 + chunk], dtype=np.float64)
+        d = g - r
+        dmax = max(dmax, float(np.max(np.abs(d))))
+        rmax = max(rmax, float(np.max(np.abs(r))))
+        dss += float(np.sum(d * d))
+        rss += float(np.sum(r * r))
+    return dmax / rmax, float(np.sqrt(dss / rss))

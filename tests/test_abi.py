@@ -31,9 +31,10 @@ def test_header_symbols_exported(L):
 
 
 def test_version_and_strerror(L):
-    assert L.mms_abi_version() == 3
-    for code in (0, -1, -2, -3, -4):
+    assert L.mms_abi_version() == 4
+    for code in (0, -1, -2, -3, -4, -5):
         assert L.mms_strerror(code)
+    assert L.mms_strerror(-5) != L.mms_strerror(-99)
 
 
 def grid(nx=16, ny=16, nz=16, H=4, sy=None, sz=None):
@@ -132,6 +133,66 @@ def test_wave_validation(L):
     assert L.mms_wave_scale_mu(ctypes.byref(w), a, b, 0, None) == -1
     assert L.mms_wave_scale_mu(ctypes.byref(w), a, vp(0x100040), 1, None) == -1  # partial overlap
     assert L.mms_wave_scale_mu(ctypes.byref(w), None, b, 1, None) == -1
+
+
+def test_reduction_validation(L):
+    """Reductions need a result pair and a workspace of their own: missing, misaligned
+    or overlapping buffers are refused before anything is enqueued."""
+    vp = ctypes.c_void_p
+    a, b = vp(0x100000), vp(0x800000)
+    out, work = vp(0x2000000), vp(0x3000000)
+    g = grid()
+    for fn, args in ((L.mms_flat_dot_f64, (a, b, 100)), (L.mms_flat_misfit_f64, (a, b, None, 100))):
+        assert fn(*args, None, work, None) == -1                   # no result pair
+        assert fn(*args, out, None, None) == -1                    # no workspace
+        assert fn(*args, vp(0x2000004), work, None) == -1          # misaligned result
+        assert fn(*args, out, vp(0x3000004), None) == -1           # misaligned workspace
+        assert fn(*args, vp(0x3000000 + 8 * 2047), work, None) == -1  # result inside the workspace
+        assert fn(*args, vp(0x3000000 - 8), work, None) == -1      # result overlaps its first word
+    assert L.mms_flat_dot_f64(a, b, -1, out, work, None) == -1
+    assert L.mms_flat_misfit_f64(a, None, None, 100, out, work, None) == -1
+    assert L.mms_dot_f64(a, b, ctypes.byref(g), out, None, None) == -1
+    assert L.mms_dot_f64(None, b, ctypes.byref(g), out, work, None) == -1
+    assert L.mms_dot_f64(a, b, ctypes.byref(grid(sy=22)), out, work, None) == -1
+    # the chain-rule scaling
+    assert L.mms_flat_scale_f32(a, None, b, 10, None) == -1
+    assert L.mms_flat_scale_f32(a, out, b, -1, None) == -1
+    assert L.mms_flat_scale_f32(a, vp(0x2000004), b, 10, None) == -1
+    assert L.mms_flat_scale_f32(a, out, vp(0x100004), 10, None) == -1   # partial overlap
+    # energy: workspace size from the grid, and the same buffer rules
+    from paper_2507_11067_amd._lib import MmsWave
+    lap = (ctypes.c_float * 5)(-2.8, 1.6, -0.2, 0.025, -0.0018)
+    w = MmsWave(grid(), 4, lap, vp(0x20000), 1.0, 0, 0.0, 0, 10, 0, 0, 0, None, None, None)
+    need = ctypes.c_int64(-1)
+    assert L.mms_wave_energy_work(ctypes.byref(w), ctypes.byref(need)) == 0
+    assert need.value >= 2 and need.value % 2 == 0
+    assert L.mms_wave_energy_work(ctypes.byref(w), None) == -1
+    assert L.mms_wave_energy(ctypes.byref(w), a, b, out, work, need.value - 1, None) == -1
+    assert L.mms_wave_energy(ctypes.byref(w), a, b, out, None, need.value, None) == -1
+    assert L.mms_wave_energy(ctypes.byref(w), a, None, out, work, need.value, None) == -1
+    assert L.mms_wave_energy(ctypes.byref(w), a, b, work, work, need.value, None) == -1
+    w.g.nx = 0
+    assert L.mms_wave_energy_work(ctypes.byref(w), ctypes.byref(need)) == 0 and need.value == 0
+
+
+def test_check_reduction_flags_nonfinite(L):
+    """The MMS_EUNSTABLE path: a result pair reporting NaN or Inf terms, or a non-finite
+    sum, is an error; a clean pair is not."""
+    pair = lambda v, c: (ctypes.c_double * 2)(v, c)
+    assert L.mms_check_reduction(pair(1.5, 0.0)) == 0
+    assert L.mms_check_reduction(pair(0.0, 0.0)) == 0
+    assert L.mms_check_reduction(pair(-1e300, 0.0)) == 0
+    assert L.mms_check_reduction(pair(1.5, 1.0)) == -5
+    assert L.mms_check_reduction(pair(float("nan"), 0.0)) == -5
+    assert L.mms_check_reduction(pair(float("inf"), 0.0)) == -5
+    assert L.mms_check_reduction(pair(float("-inf"), 2.0)) == -5
+    assert L.mms_check_reduction(None) == -1
+    import torch
+    from paper_2507_11067_amd import MmsError, check_result
+    assert check_result(torch.tensor([2.5, 0.0], dtype=torch.float64)) == 2.5
+    with pytest.raises(MmsError) as e:
+        check_result(torch.tensor([2.5, 3.0], dtype=torch.float64))
+    assert e.value.code == -5
 
 
 def test_python_binding_requires_library(monkeypatch, tmp_path):

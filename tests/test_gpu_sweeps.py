@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import synth
-from tests.helpers import halo_is_zero, interior, rel_errors
+from tests.helpers import halo_is_zero, interior, rel_errors, rel_errors_chunked
 
 pytestmark = pytest.mark.gpu
 
@@ -173,51 +173,55 @@ def test_deterministic(mms, shape, prec, r):
     assert torch.equal(a, b)
 
 
-def sample_points(rng, n, count=4000):
-    pts = rng.integers(0, n, (count, 3))
-    # always include corners and faces
-    extra = np.array([[0, 0, 0], [n - 1, n - 1, n - 1], [0, n - 1, 0], [n - 1, 0, n - 1],
-                      [n // 2, 0, n // 2], [n // 2, n // 2, n - 1]])
-    return np.concatenate([pts, extra])
-
-
 @pytest.fixture(scope="module")
 def big512():
+    """The benchmark's 512^3 input (uniform [-1, 1], seed 2) on its layout: rows padded to
+    544, interior rows on 128-byte boundaries; plus a cache of full-grid oracle sweeps."""
     n = 512
-    # the benchmark's layout: rows padded to 544, interior rows on 128-byte boundaries
     x = synth.uniform_grid(2, n, n, n, sy=((n + 8 + 31) // 32) * 32)
-    return n, x, x.astype(np.float64)
+    return {"n": n, "x": x, "x64": x.astype(np.float64), "ref": {}}
 
 
-def test_star_512_sampled(mms, big512):
-    """Full-size workload (512^3, radius-4 Laplacian) in the benchmark's launch shape."""
-    n, x, x64 = big512
+def oracle_512(big, shape, r, c):
+    """Interior of the full-grid FP64 oracle sweep, computed once per (shape, r)."""
+    key = (shape, r)
+    if key not in big["ref"]:
+        n = big["n"]
+        f = oracle.star if shape == "star" else oracle.box
+        full = f(big["x64"], n, n, n, r, c)
+        big["ref"][key] = np.ascontiguousarray(full[4:4 + n, 4:4 + n, 4:4 + n])
+        del full
+    return big["ref"][key]
+
+
+def test_star_512_full_grid(mms, big512):
+    """Full-size workload (512^3, radius-4 Laplacian) in the benchmark's launch shape, every
+    one of the 134,217,728 outputs against the full-grid FP64 oracle sweep."""
+    n = big512["n"]
     grid = mms.Grid.aligned(n, n, n)
     c = synth.star_coeffs_laplacian(4)
-    got = run(mms, x, grid, "star", 4, c)
-    pts = sample_points(np.random.default_rng(14), n)
-    ref = oracle.star_at(x64, n, n, n, 4, c, pts)
-    vals = got[pts[:, 0] + 4, pts[:, 1] + 4, pts[:, 2] + 4]
-    rmax, rrms = rel_errors(vals, ref)
+    got = run(mms, big512["x"], grid, "star", 4, c)
+    rmax, rrms = rel_errors_chunked(interior(got, grid), oracle_512(big512, "star", 4, c))
+    print(f"star r4 512^3 full grid: rel_max {rmax:.2e} rel_rms {rrms:.2e}")
     assert rmax <= TOL, rmax
     assert halo_is_zero(got, grid)
 
 
 @pytest.mark.parametrize("r,prec", [(2, "fp32"), (4, "fp32"), (3, "fp32"), (3, "bf16x3"),
                                     (4, "bf16x3"), (3, "fp16x3s"), (4, "fp16x3s"),
-                                    (4, "bf16x1")])
-def test_box_512_sampled(mms, big512, r, prec):
-    n, x, x64 = big512
+                                    (4, "bf16x1"), (3, "bf16x1")])
+def test_box_512_full_grid(mms, big512, r, prec):
+    """Every output of the 512^3 box sweeps (the headline's radius-2 and radius-4 FP32
+    boxes, and radius 3 and 4 in each split precision) against the full-grid FP64 oracle."""
+    n = big512["n"]
     grid = mms.Grid.aligned(n, n, n)
     c = synth.box_coeffs({2: 3, 3: 6, 4: 4}[r], r)
-    got = run(mms, x, grid, "box", r, c, prec)
-    pts = sample_points(np.random.default_rng(15 + r), n, 2000)
-    ref = oracle.box_at(x64, n, n, n, r, c, pts)
-    vals = got[pts[:, 0] + 4, pts[:, 1] + 4, pts[:, 2] + 4]
-    rmax, rrms = rel_errors(vals, ref)
-    print(f"box r{r} {prec} 512^3 sampled: rel_max {rmax:.2e} rel_rms {rrms:.2e}")
+    got = run(mms, big512["x"], grid, "box", r, c, prec)
+    rmax, rrms = rel_errors_chunked(interior(got, grid), oracle_512(big512, "box", r, c))
+    print(f"box r{r} {prec} 512^3 full grid: rel_max {rmax:.2e} rel_rms {rrms:.2e}")
+    assert halo_is_zero(got, grid)
     if prec == "bf16x1":
-        assert rmax < 2e-2
+        assert rmax < 2e-2      # the reduced-accuracy variant: reported, near its 2e-3 level
     else:
         assert rmax <= TOL, rmax
 

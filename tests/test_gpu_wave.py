@@ -140,7 +140,7 @@ def test_reductions(mms):
     y = np.random.default_rng(2).standard_normal(100003).astype(np.float32)
     assert mms.flat_dot(T(x), T(y)) == pytest.approx(np.dot(x.astype(np.float64), y), rel=1e-12)
     r = torch.empty(100003, device=DEV)
-    J = mms.flat_misfit(T(x), T(y), resid=r).item()
+    J = mms.check_result(mms.flat_misfit(T(x), T(y), resid=r))
     ref = 0.5 * np.sum((x - y).astype(np.float64) ** 2)
     assert J == pytest.approx(ref, rel=1e-12)
     np.testing.assert_array_equal(r.cpu().numpy(), x - y)
@@ -249,9 +249,9 @@ def autograd_problem(mms, n, nt, seed, K, W=8):
 @pytest.mark.parametrize("form", ["lam", "mu"])
 def test_checkpointing_gives_identical_gradient(mms, form):
     """Segment length, or keeping every level resident (store_all, no recompute), changes only
-    where the forward levels come from: the lam-form gradient is bit-identical; the mu form
-    scales the FP64 sum by c2 and back once per segment, so its FP64 sums may differ in the
-    last bits, which FP32 output hides or shows as one ulp."""
+    where the forward levels come from and how the adjoint steps are split over calls: the
+    gradient is bit-identical in both forms (the blocks of FP32 partial sums run across call
+    boundaries, and the mu form divides by c2 where a block's sum reaches the FP64 gradient)."""
     from paper_2507_11067_amd.autograd import misfit, propagate
     n, nt = 32, 120
     s, grid, m, prob = autograd_problem(mms, n, nt, 40, K=50)
@@ -269,11 +269,7 @@ def test_checkpointing_gives_identical_gradient(mms, form):
         grads.append((mt.grad.clone(), z0.grad.clone(), z1.grad.clone()))
     for gk in grads[1:]:
         for a, b in zip(grads[0], gk):
-            if form == "lam":
-                assert torch.equal(a, b)
-            else:
-                ulp = torch.finfo(torch.float32).eps * a.abs().max()
-                assert (a - b).abs().max() <= ulp
+            assert torch.equal(a, b)
     assert torch.count_nonzero(grads[0][0]) > 0
     assert prob.stats["adjoint_form"] == form
     assert prob.stats["recomputed_steps"] == 0          # the store_all pass recomputed nothing
