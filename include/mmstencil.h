@@ -307,6 +307,22 @@ int mms_wave_energy(const mms_wave *w, const float *u_n, const float *u_np1, dou
                     double *work, int64_t work_elems, void *stream);
 
 /*
+ * mms_wave_energy_noalloc -- mms_wave_energy for callers that cannot allocate device
+ * memory or pass a workspace (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the per-block partials go to a static device array
+ * of 65536 doubles (512 KiB) that every GPU the library runs on holds until the process
+ * ends.  Grids whose energy needs more than that (mms_wave_energy_work > 65536, i.e.
+ * more than 32768 blocks) are refused with MMS_EINVAL before anything is enqueued, and
+ * mms_last_error names the sizes.  The call allocates nothing.  Every call on one GPU
+ * uses that GPU's array, so calls that overlap on one GPU (other streams, other
+ * threads) race and may return wrong sums; calls in stream order are safe (each call
+ * writes every partial it reads).  The first call on a device looks up the array's
+ * address there (hipGetSymbolAddress).
+ */
+int mms_wave_energy_noalloc(const mms_wave *w, const float *u_n, const float *u_np1,
+                            double *out_dev, void *stream);
+
+/*
  * mms_check_reduction -- host helper: MMS_EUNSTABLE if a reduction's result pair
  * (copied to the host) reports non-finite terms or a non-finite sum, MMS_OK
  * otherwise, MMS_EINVAL for NULL.
@@ -347,7 +363,8 @@ int mms_grid_aligned(int64_t nx, int64_t ny, int64_t nz, int32_t halo, mms_grid 
                      int64_t *lead);
 
 const char *mms_strerror(int code);
-const char *mms_last_error(void); /* text of the last MMS_EHIP on this thread */
+const char *mms_last_error(void); /* text of the last MMS_EHIP on this thread, or of a */
+                                  /* size refusal of mms_wave_energy_noalloc            */
 int mms_abi_version(void);
 
 #ifdef __cplusplus

@@ -16,7 +16,8 @@ EXPORTS = ("mms_stencil_apply", "mms_wave_step", "mms_wave_record", "mms_wave_fo
            "mms_wave_energy", "mms_dot_f64",
            "mms_flat_dot_f64", "mms_flat_misfit_f64", "mms_dense_to_grid", "mms_grid_aligned",
            "mms_strerror", "mms_last_error", "mms_abi_version", "mms_vti_step", "mms_tti_step",
-           "mms_wave_energy_work", "mms_flat_scale_f32", "mms_check_reduction")
+           "mms_wave_energy_work", "mms_flat_scale_f32", "mms_check_reduction",
+           "mms_wave_energy_noalloc")
 
 
 class MmsGrid(ctypes.Structure):
@@ -75,6 +76,7 @@ def lib():
         L.mms_grid_aligned.argtypes = [i64, i64, i64, ctypes.c_int32, gp, ctypes.POINTER(i64)]
         L.mms_wave_energy_work.argtypes = [wp, ctypes.POINTER(i64)]
         L.mms_wave_energy.argtypes = [wp, vp, vp, vp, vp, i64, vp]
+        L.mms_wave_energy_noalloc.argtypes = [wp, vp, vp, vp, vp]
         L.mms_vti_step.argtypes = [wp, i32] + [vp] * 8 + [vp]
         L.mms_tti_step.argtypes = [wp, ctypes.POINTER(MmsTti), i32] + [vp] * 6 + [vp]
         L.mms_dot_f64.argtypes = [vp, vp, gp, vp, vp, vp]

@@ -5,6 +5,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
+
 #include "mms_internal.h"
 
 namespace mms {
@@ -33,6 +35,42 @@ int flat_scale(const float *in, const double *scale, float *out, int64_t n, hipS
 
 namespace {
 thread_local char g_last[256] = "";
+}  // namespace
+
+// Scratch of mms_wave_energy_noalloc: the energy kernel's per-block (partial sum,
+// non-finite count) pairs, in a static device array instead of a caller workspace.
+// Every GPU the library runs on holds its own copy (512 KiB) until the process ends.
+constexpr int64_t kEnergyScratch = 1 << 16;  // doubles: grids of up to 32768 energy blocks
+static __device__ __align__(256) double scratch[kEnergyScratch];
+
+namespace {
+// Device address of `scratch` per device: the host-side name is only a stand-in, so the
+// address is looked up once per device (with that device current) and reused.
+constexpr int kMaxDev = 64;
+std::atomic<double *> g_scratch[kMaxDev];
+
+int scratch_address(double **p) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDev) {
+        snprintf(g_last, sizeof g_last, "device %d beyond the %d devices with a scratch address",
+                 dev, kMaxDev);
+        return MMS_EINVAL;
+    }
+    double *q = g_scratch[dev].load(std::memory_order_acquire);
+    if (!q) {
+        e = hipGetSymbolAddress((void **)&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!q) {
+            snprintf(g_last, sizeof g_last, "hipGetSymbolAddress(scratch) gave a null address");
+            return MMS_EHIP;
+        }
+        g_scratch[dev].store(q, std::memory_order_release);
+    }
+    *p = q;
+    return MMS_OK;
+}
 }  // namespace
 
 int hip_fail(hipError_t e, const char *where) {
@@ -334,6 +372,26 @@ int mms_dense_to_grid(const double *in, float *out, const mms_grid *g, double sc
     if (g->ny > 65535 || g->nz > 65535) return MMS_EINVAL;
     if (grid_empty(g)) return MMS_OK;
     return dense_to_grid(in, out, g, scale, (hipStream_t)stream);
+}
+
+int mms_wave_energy_noalloc(const mms_wave *w, const float *u_n, const float *u_np1,
+                            double *out_dev, void *stream) {
+    if (int rc = wave_ok(w)) return rc;
+    if (!u_n || !u_np1 || !out_dev || !aligned8(out_dev)) return MMS_EINVAL;
+    int64_t need = 0;
+    if (int rc = mms_wave_energy_work(w, &need)) return rc;
+    if (need > kEnergyScratch) {
+        snprintf(g_last, sizeof g_last,
+                 "mms_wave_energy_noalloc: the grid needs %lld doubles of scratch, the static "
+                 "scratch holds %lld (use mms_wave_energy with a workspace)",
+                 (long long)need, (long long)kEnergyScratch);
+        return MMS_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (grid_empty(&w->g)) return fill_pair(out_dev, 0.0, s);
+    double *ptr = nullptr;
+    if (int rc = scratch_address(&ptr)) return rc;
+    return wave_energy(w, u_n, u_np1, out_dev, ptr, s);
 }
 
 int mms_dot_f64(const float *a, const float *b, const mms_grid *g, double *out_dev, double *work,

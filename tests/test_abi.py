@@ -231,3 +231,25 @@ def test_grid_aligned_layout(L):
     for args in [(-1, 1, 1, 4), (1, 1, 1, 2), (1, 1, 1, 0), (1, -1, 1, 4)]:
         assert L.mms_grid_aligned(*args, ctypes.byref(g), ctypes.byref(lead)) == -1
     assert L.mms_grid_aligned(1, 1, 1, 4, None, ctypes.byref(lead)) == -1
+
+
+def test_energy_noalloc_refuses_grids_beyond_its_scratch(L):
+    """The no-allocation energy refuses, before any HIP call, a grid whose per-block
+    partials do not fit its static scratch (4096^3: 131072 blocks), and names the sizes."""
+    from paper_2507_11067_amd._lib import MmsWave
+    vp = ctypes.c_void_p
+    lap = (ctypes.c_float * 5)(-2.8, 1.6, -0.2, 0.025, -0.0018)
+    big = grid(4096, 4096, 4096)
+    w = MmsWave(big, 4, lap, vp(0x20000), 1.0, 0, 0.0, 0, 10, 0, 0, 0, None, None, None)
+    need = ctypes.c_int64(0)
+    assert L.mms_wave_energy_work(ctypes.byref(w), ctypes.byref(need)) == 0
+    assert need.value > 65536
+    assert L.mms_wave_energy_noalloc(ctypes.byref(w), vp(0x100000), vp(0x800000),
+                                     vp(0x2000000), None) == -1
+    msg = L.mms_last_error().decode()
+    assert str(need.value) in msg and "65536" in msg
+    small = MmsWave(grid(), 4, lap, vp(0x20000), 1.0, 0, 0.0, 0, 10, 0, 0, 0, None, None, None)
+    assert L.mms_wave_energy_noalloc(ctypes.byref(small), vp(0x100000), None, vp(0x2000000),
+                                     None) == -1
+    assert L.mms_wave_energy_noalloc(ctypes.byref(small), vp(0x100000), vp(0x800000),
+                                     vp(0x2000004), None) == -1      # misaligned result pair
