@@ -4,10 +4,12 @@ adjoint wave kernels (torch.autograd.Function), with checkpoint/recompute.
 WavePropagate.apply(m, u0, u1, problem) -> traces [nt, ny, nx]
     m = v^2 on the padded grid (FP32); u0, u1 = the first two wavefield levels.
     Backward returns dJ/dm, dJ/du0, dJ/du1 for any loss J of the traces, from
-    the exact discrete adjoint, not from a self-adjoint shortcut.  Where m > 0
-    on the whole interior the adjoint runs in mu = C2 G lam
-    (mms_wave_adjoint_mu: the forward step's form, one fewer field stream per
-    step), otherwise in lam (mms_wave_adjoint).
+    the exact discrete adjoint, not from a self-adjoint shortcut.  By default
+    the adjoint runs in mu = C2 G lam (mms_wave_adjoint_mu: the forward step's
+    form, one fewer field stream per step, and the more accurate of the two in
+    the dot-product test), which needs m > 0 on the whole interior (true for
+    m = v^2); adjoint_form="lam" runs mms_wave_adjoint for any m, and "auto"
+    checks m on the device and picks one (a host synchronisation).
 
 Memory plan: the forward pass keeps the pair (u^k, u^{k+1}) at every level
 k = 0, K, 2K, ... .  The backward pass walks the segments [k, k+K) from the
@@ -46,7 +48,7 @@ class Problem:
     sponge_faces: int = 0
     checkpoint_every: int = 50
     grad_block: int = 8        # adjoint steps whose gradient terms are summed in FP32
-    adjoint_form: str = "auto"  # "mu" (needs m > 0 on the interior), "lam", or "auto"
+    adjoint_form: str = "mu"   # "mu" (needs m > 0 on the interior), "lam", or "auto"
     store_all: bool = False    # keep every forward level resident (nt + 1 grids), no recompute
     stats: dict = field(default_factory=dict)
 
@@ -109,10 +111,11 @@ class WavePropagate(torch.autograd.Function):
         H = g.halo
         if prob.adjoint_form not in ("auto", "mu", "lam"):
             raise ValueError(f"adjoint_form {prob.adjoint_form!r}")
-        positive = prob.adjoint_form != "lam" and bool((m[H:H + g.nz, H:H + g.ny, H:H + g.nx] > 0).all())
-        if prob.adjoint_form == "mu" and not positive:
-            raise ValueError("adjoint_form 'mu' needs m > 0 on the whole interior")
-        mu_form = positive
+        if prob.adjoint_form == "auto":
+            # the one host synchronisation of a backward pass, only when asked for
+            mu_form = bool((m[H:H + g.nz, H:H + g.ny, H:H + g.nx] > 0).all())
+        else:
+            mu_form = prob.adjoint_form == "mu"
         adjoint = wa.adjoint_mu if mu_form else wa.adjoint
         lam = [g.zeros(dev) for _ in range(3)]   # lam^n (or mu^n) lives in lam[n % 3]
         seg = [] if ctx.levels is not None else [g.zeros(dev) for _ in range(min(K, max(nt, 1)))]

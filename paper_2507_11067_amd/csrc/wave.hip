@@ -322,17 +322,14 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                                                : a.c2s * gz * gown[e] * p0v[e] * o[e];
                         // mu form: c2 G lam^{n+1} S(u^n) = mu^{n+1} S(u^n) / c2, with c2 the field
                         // (C2 = c2s c2); the division is done in FP64 where a sum reaches acc64,
-                        // so the c2 field is read once per block of steps, not every step
-                        double rc2[4] = {1.0, 1.0, 1.0, 1.0};
-                        if (MODE == MODE_GRAD && a.mu_form && (!a.part || a.part_last)) {
-                            const float4 cf = ld(a.c2, z, own_off, own_ok);
-                            rc2[0] = 1.0 / (double)cf.x;
-                            rc2[1] = 1.0 / (double)cf.y;
-                            rc2[2] = 1.0 / (double)cf.z;
-                            rc2[3] = 1.0 / (double)cf.w;
-                        }
+                        // so the c2 field is read (cell by cell) once per block of steps
+                        const bool div_c2 = MODE == MODE_GRAD && a.mu_form;
+                        const float *c2row = a.c2 + (int64_t)z * sz + own_off;
+                        auto fin = [&](int e, double v) -> double {
+                            return div_c2 ? v / (double)c2row[e] : v;
+                        };
                         auto t64 = [&](int e) -> double {
-                            return MODE == MODE_FWD ? (double)r[e] * (double)r[e] : (double)t[e] * rc2[e];
+                            return MODE == MODE_FWD ? (double)r[e] * (double)r[e] : fin(e, (double)t[e]);
                         };
                         double *pa = a.acc64 + dense;
                         // four cells in range on a 16-byte aligned dense row: one 16-byte
@@ -368,10 +365,10 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                                 if (a.part_last) {
                                     double2 *p2 = reinterpret_cast<double2 *>(pa);
                                     double2 lo = p2[0], hi = p2[1];
-                                    lo.x += (double)sum[0] * rc2[0];
-                                    lo.y += (double)sum[1] * rc2[1];
-                                    hi.x += (double)sum[2] * rc2[2];
-                                    hi.y += (double)sum[3] * rc2[3];
+                                    lo.x += fin(0, (double)sum[0]);
+                                    lo.y += fin(1, (double)sum[1]);
+                                    hi.x += fin(2, (double)sum[2]);
+                                    hi.y += fin(3, (double)sum[3]);
                                     p2[0] = lo;
                                     p2[1] = hi;
                                 } else {
@@ -383,7 +380,7 @@ __global__ void __launch_bounds__(TX *TY) wave_kernel(WaveArgs a) {
                                     if (x0 + e < g.nx) {
                                         const float sum = a.part_first ? t[e] : pp[e] + t[e];
                                         if (a.part_last)
-                                            pa[e] += (double)sum * rc2[e];
+                                            pa[e] += fin(e, (double)sum);
                                         else
                                             pp[e] = sum;
                                     }

@@ -3,9 +3,11 @@
 15 Hz Ricker source at 50 m depth, Courant 0.4, receivers on the top interior plane,
 checkpoints every 50 steps.
 
-  * dot-product test of the adjoint, <A x, y> = <x, A^T y> to 1e-5 relative, in both the lam
-    and the mu form (x = two smooth random initial levels, y = the scattered-field residual
-    of the perturbed model, A = initial levels -> receiver traces at fixed m);
+  * dot-product test of the adjoint, <A x, y> = <x, A^T y> to 1e-5 relative, in both the mu
+    and the lam form (x = two smooth random initial levels, A = initial levels -> receiver
+    traces at fixed m, y = A x plus the scattered-field residual of the perturbed model
+    scaled to the same norm; with y = the residual alone the pairing is ill-conditioned and
+    the error is gated relative to |A x| |y|);
   * central finite differences of the misfit along Gaussian bumps (sigma 2 cells, amplitude
     1 % of m) at 16 points where the gradient is large, against <dJ/dm, bump>, gate 5e-2;
   * a Taylor test along a smooth direction: the remainder J(m + e dm) - J(m) - e <g, dm>
@@ -46,10 +48,15 @@ def work():
             "resid": (d - d_obs).contiguous()}
 
 
-@pytest.mark.parametrize("form", ["lam", "mu"])
+@pytest.mark.parametrize("form", ["mu", "lam"])
 def test_dot_product_256_1000(work, form):
+    """<A x, y> = <x, A^T y>, x = (u^0, u^1) two smooth random levels (seeds 81, 82).
+    (a) y = A x + r', with r' the scattered-field residual scaled to the norm of A x: the
+        relative error |lhs - rhs| / |lhs|, gated at 1e-5;
+    (b) y = the residual alone: x and y are unrelated, so |<A x, y>| is only about 1e-4 to
+        1e-2 of |A x| |y| and the relative error is amplified by its inverse; this case is
+        gated on |lhs - rhs| / (|A x| |y|) <= 1e-7, and its relative error is printed."""
     mms, s, grid = work["mms"], work["s"], work["grid"]
-    y = work["resid"]
     w = mms.Wave(grid, work["m"], LAP, NT, (s.dt / s.h) ** 2, s.sponge_width, s.sponge_alpha,
                  s.sponge_faces, s.src, None, torch.zeros((NT, N, N), device=DEV))
     u0 = torch.from_numpy(synth.smooth_random_grid(81, N, N, N, sigma=3.0)).to(DEV)
@@ -57,18 +64,29 @@ def test_dot_product_256_1000(work, form):
     bufs = [u0.clone(), u1.clone(), grid.zeros(DEV)]
     w.record(0, bufs[0])
     w.forward(1, NT, [bufs[i % 3] for i in range(NT + 1)])
-    lhs = mms.flat_dot(w.traces, y)
-    lam = [grid.zeros(DEV) for _ in range(3)]
-    if form == "lam":
-        w.adjoint(NT - 1, 0, [lam[i % 3] for i in range(NT + 2)], resid=y)
-    else:
-        w.adjoint_mu(NT - 1, 0, [lam[i % 3] for i in range(NT + 2)], resid=y)
-        w.scale_mu(lam[0], lam[0], -1)
-        w.scale_mu(lam[1], lam[1], -1)
-    rhs = mms.dot(u0, lam[0], grid) + mms.dot(u1, lam[1], grid)
-    rel = abs(lhs - rhs) / abs(lhs)
-    print(f"dot test 256^3 x {NT}, {form} form: lhs {lhs:.10e} rhs {rhs:.10e} rel {rel:.2e}")
-    assert rel <= 1e-5, rel
+    ax = w.traces.clone()
+    r = work["resid"]
+    nax = mms.flat_dot(ax) ** 0.5
+    nr = mms.flat_dot(r) ** 0.5
+    for name, y in (("Ax + residual", (ax + r * (nax / nr)).contiguous()), ("residual", r)):
+        lhs = mms.flat_dot(ax, y)
+        lam = [grid.zeros(DEV) for _ in range(3)]
+        if form == "lam":
+            w.adjoint(NT - 1, 0, [lam[i % 3] for i in range(NT + 2)], resid=y)
+        else:
+            w.adjoint_mu(NT - 1, 0, [lam[i % 3] for i in range(NT + 2)], resid=y)
+            w.scale_mu(lam[0], lam[0], -1)
+            w.scale_mu(lam[1], lam[1], -1)
+        rhs = mms.dot(u0, lam[0], grid) + mms.dot(u1, lam[1], grid)
+        ny = mms.flat_dot(y) ** 0.5
+        rel, nrm, cond = abs(lhs - rhs) / abs(lhs), abs(lhs - rhs) / (nax * ny), abs(lhs) / (nax * ny)
+        print(f"dot test 256^3 x {NT}, {form} form, y = {name}: lhs {lhs:.10e} rhs {rhs:.10e} "
+              f"rel {rel:.2e} normalised {nrm:.2e} (|lhs|/(|Ax||y|) {cond:.2e})")
+        if name == "residual":
+            assert nrm <= 1e-7, nrm
+        else:
+            assert cond > 0.5
+            assert rel <= 1e-5, rel
 
 
 def test_gradient_fd_and_taylor_256_1000(work):
