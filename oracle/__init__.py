@@ -21,6 +21,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mms_oracle.c")
 _LIB = os.path.join(_HERE, "libmms_oracle.so")
+# a prebuilt oracle library to load instead (the sanitizer test builds one with
+# -fsanitize=address,undefined and runs the pins against it in a child process)
+_LIB_OVERRIDE = os.environ.get("MMS_ORACLE_LIB")
 _lib = None
 
 
@@ -58,8 +61,11 @@ class _Tti(ctypes.Structure):
 def _load():
     global _lib
     if _lib is None:
-        build(force=False)
-        lib = ctypes.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            lib = ctypes.CDLL(_LIB_OVERRIDE)
+        else:
+            build(force=False)
+            lib = ctypes.CDLL(_LIB)
         gp = ctypes.POINTER(_Grid)
         wp = ctypes.POINTER(_Wave)
         lib.orc_star.argtypes = [_dp, _dp, gp, ctypes.c_int, _dp]
