@@ -62,7 +62,7 @@ def parse():
     p.add_argument("--steps", type=int, default=100)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--n", type=int, default=512, help="headline grid edge")
-    p.add_argument("--only", default="", help="profile one kernel: star|box2|box4|box4_bf16x3|"
+    p.add_argument("--only", default="", help="profile one kernel: star|box2|box3|box4|box4_bf16x3|"
                    "box4_fp16x3s|box3_bf16x3|wave|vti|copy|2DStarR2|2DStarR4|2DBoxR2|2DBoxR3|"
                    "3DStarR2|3DBoxR1|tti")
     p.add_argument("--skip", default="", help="comma list of extras to skip: "
@@ -847,6 +847,7 @@ COUNTED = {
     "star": ("star.hip", "star_kernel<4", 8.0),
     "box2": ("box_valu.hip", "box_valu_kernel<2", 8.0),
     "box4": ("box_valu.hip", "box_valu_kernel<4", 8.0),
+    "box3": ("box_valu.hip", "box_valu_kernel<3", 8.0),
     "box4_bf16x3": ("box_mfma.hip", "box_mfma_kernel<4, 1,", 8.0),
     "box3_bf16x3": ("box_mfma.hip", "box_mfma_kernel<3, 1,", 8.0),
     "wave": ("wave.hip", "wave_kernel<4, 0, 64", 16.0),   # 400^3 forward step, no image
@@ -894,6 +895,8 @@ UTIL_PASSES = {
     "box4_bf16x3": "MfmaUtil SQ_INSTS_VALU_MFMA_MOPS_BF16 LDSBankConflict",
     "box3_bf16x3": "MfmaUtil SQ_INSTS_VALU_MFMA_MOPS_BF16 LDSBankConflict",
     "box4": "VALUBusy SQ_INSTS_VALU_FMA_F32 LDSBankConflict",
+    "box3": "VALUBusy SQ_INSTS_VALU_FMA_F32 LDSBankConflict",
+    "box2": "VALUBusy SQ_INSTS_VALU_FMA_F32 LDSBankConflict",
     "star": "VALUBusy LDSBankConflict",
 }
 
@@ -1078,6 +1081,8 @@ def profile_only(args, torch, mms, synth, grid, x, outs, sweeps, c_box4, c_box3,
         prec = k.split("_", 1)[1]
         c = c_box4 if r == 4 else c_box3
         f = lambda: mms.stencil_apply(x, out, grid, "box", r, c, precision=prec)
+    elif k == "box3":
+        f = lambda: mms.stencil_apply(x, out, grid, "box", 3, c_box3)
     elif k == "copy":
         ca = x.reshape(-1).clone()      # flat buffers of the grid's size, allocator-aligned
         cb = torch.empty_like(ca)

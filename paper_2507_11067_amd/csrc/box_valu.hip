@@ -6,13 +6,14 @@
 // kernel follows the box decomposition of Sec. IV-C: the box is (2r+1)^2
 // one-dimensional x stencils, one per (dz, dy) pair, and each loaded input row
 // feeds all of them before it is dropped:
-//  * a block owns a (4*TX) x TY tile and streams z; one input plane of the tile
+//  * a block owns a (4*TX) x (TY*rows) tile and streams z; one input plane of the tile
 //    (plus 4 cells of x halo and r rows of y halo) sits in LDS at a time,
 //    double-buffered, one barrier per plane;
-//  * each lane owns 4 consecutive x of one row and keeps 2r+1 partial sums for
-//    the 2r+1 output planes the current input plane feeds (input plane z'
-//    contributes to output z'-dz through weights c[dz]); the oldest sum is
-//    complete after each plane and the window shifts by one;
+//  * each lane owns 4 consecutive x of one row (of two rows at radius 2 and 3)
+//    and keeps 2r+1 partial sums per row for the 2r+1 output planes the current
+//    input plane feeds (input plane z' contributes to output z'-dz through
+//    weights c[dz]); the oldest sum is complete after each plane and the window
+//    shifts by one;
 //  * a lane reads 12 consecutive cells of one input row (three 16-byte LDS
 //    words) and applies all (2r+1) x (2r+1) weights of that dy to them, so LDS
 //    traffic is 3 words per (2r+1)^2 * 4 FMAs.
@@ -38,11 +39,11 @@ struct BoxArgs {
     float c[729];  // [dz][dy][dx] for radius r, (2r+1)^3 used
 };
 
-template <int R, int TX, int TY, bool LDSW>
+template <int R, int TX, int TY, bool LDSW, int NYL>
 __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
     constexpr int W = 2 * R + 1;
     constexpr int BX = 4 * TX;
-    constexpr int BY = TY;
+    constexpr int BY = TY * NYL;              // NYL output rows per lane
     constexpr int LW4 = TX + 2;
     constexpr int LH = BY + 2 * R;
     constexpr int NT = TX * TY;
@@ -61,7 +62,7 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
     const int xt = txi * BX, yt = tyi * BY;
-    const int x0 = xt + 4 * tx, y = yt + ty;
+    const int x0 = xt + 4 * tx, y = yt + NYL * ty;   // the lane's rows: y .. y + NYL - 1
     const int zb = zci * g.zchunk;
     const int ze = min(zb + g.zchunk, g.nz);
     const int nx4 = (g.nx + 3) & ~3;
@@ -103,11 +104,13 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
     using S0 = std::integral_constant<int, 0>;
     using S1 = std::integral_constant<int, NSB - 1>;
 
-    float acc[W][4];
+    float acc[W][NYL][4];
 #pragma unroll
     for (int s = 0; s < W; ++s)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[s][e] = 0.f;
+        for (int j = 0; j < NYL; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[s][j][e] = 0.f;
 
     const int z_first = zb - R, z_last = ze + R;  // input planes [z_first, z_last)
     load_plane(z_first, S0{});
@@ -137,9 +140,17 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
             constexpr int DYU = (LDSW && (R == 2 || R == 4)) ? 2 * R + 1 : 1;
 #pragma unroll DYU
             for (int dy = -R; dy <= R; ++dy) {
-                const float4 *row = t + (ty + R + dy) * LW4;
-                const float4 L = row[tx], C = row[tx + 1], Rr = row[tx + 2];
-                const float w[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w, Rr.x, Rr.y, Rr.z, Rr.w};
+                // input rows y + j + dy (j < NYL): each weight below feeds 4 NYL FMAs
+                float w[NYL][12];
+#pragma unroll
+                for (int j = 0; j < NYL; ++j) {
+                    const float4 *row = t + (NYL * ty + j + R + dy) * LW4;
+                    const float4 L = row[tx], C = row[tx + 1], Rr = row[tx + 2];
+                    const float v[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w,
+                                         Rr.x, Rr.y, Rr.z, Rr.w};
+#pragma unroll
+                    for (int i = 0; i < 12; ++i) w[j][i] = v[i];
+                }
                 const float *cdy = a.c + (dy + R) * W;
 #pragma unroll
                 for (int dz = -R; dz <= R; ++dz) {
@@ -152,8 +163,10 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
                     for (int dx = -R; dx <= R; ++dx) {
                         const float ck = cc[dx + R];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            acc[R - dz][e] = fmaf(ck, w[4 + e + dx], acc[R - dz][e]);
+                        for (int j = 0; j < NYL; ++j)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                acc[R - dz][j][e] = fmaf(ck, w[j][4 + e + dx], acc[R - dz][j][e]);
                     }
                 }
             }
@@ -164,23 +177,30 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
             plane(std::true_type{});
         // output plane zi - R is complete
         const int zo = zi - R;
-        if (zo >= zb && y < g.ny && x0 < g.nx) {
-            float *po = g.out0 + (int64_t)zo * sz + (int64_t)y * sy + x0;
-            if (x0 + 3 < g.nx) {
-                *reinterpret_cast<float4 *>(po) =
-                    make_float4(acc[0][0], acc[0][1], acc[0][2], acc[0][3]);
-            } else {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    if (x0 + e < g.nx) po[e] = acc[0][e];
+        for (int j = 0; j < NYL; ++j) {
+            if (zo >= zb && y + j < g.ny && x0 < g.nx) {
+                float *po = g.out0 + (int64_t)zo * sz + (int64_t)(y + j) * sy + x0;
+                if (x0 + 3 < g.nx) {
+                    *reinterpret_cast<float4 *>(po) =
+                        make_float4(acc[0][j][0], acc[0][j][1], acc[0][j][2], acc[0][j][3]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (x0 + e < g.nx) po[e] = acc[0][j][e];
+                }
             }
         }
 #pragma unroll
         for (int s = 0; s + 1 < W; ++s)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) acc[s][e] = acc[s + 1][e];
+            for (int j = 0; j < NYL; ++j)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) acc[W - 1][e] = 0.f;
+                for (int e = 0; e < 4; ++e) acc[s][j][e] = acc[s + 1][j][e];
+#pragma unroll
+        for (int j = 0; j < NYL; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[W - 1][j][e] = 0.f;
         if (more) store_plane(buf ^ 1, std::integral_constant<int, NSB == 2 ? (sp ^ 1) : 0>{});
         __syncthreads();
     };
@@ -202,11 +222,22 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
     (void)ylim;
 }
 
+// Output rows per lane: with two, each weight loaded from LDS feeds 8 FMAs and each
+// plane's fixed work (barrier, accumulator shift, stores) is shared by twice the outputs.
+// Measured at 512^3 (warm clocks, outputs bit-identical): radius 3 109 -> 117 Gpoints/s
+// (157 VGPRs, 3 waves per SIMD), radius 2 284 -> 290; radius 4 unchanged at 219 VGPRs and
+// 2 waves per SIMD, so it keeps one row; radius 1 is bound by HBM.
+template <int R>
+struct BoxRows {
+    static constexpr int NYL = (R == 2 || R == 3) ? 2 : 1;
+};
+
 template <int R>
 int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeffs, hipStream_t s) {
     // radius 1 is bound by HBM: wide 256 x 16 tiles (1024 threads) cut the halo share
     // (measured at 512^3: 576 Gpoints/s against 513 with 64 x 16 tiles)
     constexpr int TX = R == 1 ? 64 : 16, TY = 16;
+    constexpr int NYL = BoxRows<R>::NYL;
     constexpr int W = 2 * R + 1;
     BoxArgs a{};
     Geom &g = a.g;
@@ -219,9 +250,11 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     g.sy = gd->sy;
     g.sz = gd->sz;
     g.ntx = (g.nx + 4 * TX - 1) / (4 * TX);
-    g.nty = (g.ny + TY - 1) / TY;
+    g.nty = (g.ny + TY * NYL - 1) / (TY * NYL);
     const int64_t cols = (int64_t)g.ntx * g.nty;
-    int zc = (int)((int64_t)g.nz * cols / 4096);
+    // about 4096 blocks of one output row per lane (2048 of two); a round model of the
+    // resident blocks (as in the 2-D sweeps) measured no faster at 512^3
+    int zc = (int)((int64_t)g.nz * cols * NYL / 4096);
     zc = zc < 16 ? 16 : zc;
     // radius 1 is bound by HBM: long chunks cut the re-read halo planes
     // (measured at 512^3: 512 Gpoints/s at 128 planes against 441 at 32)
@@ -232,8 +265,8 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     const int64_t nblk = (int64_t)g.ntx * g.nty * g.nzc;
     if (nblk > 0x7fffffff) return MMS_EINVAL;
     constexpr bool LDSW = R >= 2;
-    hipLaunchKernelGGL((box_valu_kernel<R, TX, TY, LDSW>), dim3((unsigned)nblk), dim3(TX * TY), 0, s,
-                       a);
+    hipLaunchKernelGGL((box_valu_kernel<R, TX, TY, LDSW, NYL>), dim3((unsigned)nblk), dim3(TX * TY),
+                       0, s, a);
     return check_launch("box_valu_kernel");
 }
 
