@@ -201,26 +201,34 @@ __global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
     }
 
     float4 stage[NSK];
+    uint2 shi[NSK], slo[NSK];   // the staged plane split into packed 16-bit hi and lo parts
     auto load_plane = [&](int z) {
         const float *p = g.in0 + (int64_t)z * sz;
 #pragma unroll
         for (int k = 0; k < NSK; ++k) stage[k] = guarded_load(p + s_off[k], s_ok[k], g.in0);
     };
-    auto store_plane = [&]() {
+    // the split runs while the previous plane's MFMAs execute; only the LDS writes wait
+    // for the barrier that frees the plane buffer
+    auto split_plane = [&]() {
+#pragma unroll
+        for (int k = 0; k < NSK; ++k) {
+            uint16_t h0, l0, h1, l1, h2, l2, h3, l3;
+            split<PREC>(stage[k].x, dscale, h0, l0);
+            split<PREC>(stage[k].y, dscale, h1, l1);
+            split<PREC>(stage[k].z, dscale, h2, l2);
+            split<PREC>(stage[k].w, dscale, h3, l3);
+            shi[k] = make_uint2(h0 | (uint32_t)h1 << 16, h2 | (uint32_t)h3 << 16);
+            slo[k] = make_uint2(l0 | (uint32_t)l1 << 16, l2 | (uint32_t)l3 << 16);
+        }
+    };
+    auto write_plane = [&]() {
 #pragma unroll
         for (int k = 0; k < NSK; ++k) {
             const int i = tid + k * NTH;
             if (i < NS) {
                 const int row = i / C4, col = i % C4;
-                uint16_t h0, l0, h1, l1, h2, l2, h3, l3;
-                split<PREC>(stage[k].x, dscale, h0, l0);
-                split<PREC>(stage[k].y, dscale, h1, l1);
-                split<PREC>(stage[k].z, dscale, h2, l2);
-                split<PREC>(stage[k].w, dscale, h3, l3);
-                *reinterpret_cast<uint2 *>(&sm.dhi[row][4 * col]) =
-                    make_uint2(h0 | (uint32_t)h1 << 16, h2 | (uint32_t)h3 << 16);
-                *reinterpret_cast<uint2 *>(&sm.dlo[row][4 * col]) =
-                    make_uint2(l0 | (uint32_t)l1 << 16, l2 | (uint32_t)l3 << 16);
+                *reinterpret_cast<uint2 *>(&sm.dhi[row][4 * col]) = shi[k];
+                *reinterpret_cast<uint2 *>(&sm.dlo[row][4 * col]) = slo[k];
             }
         }
     };
@@ -237,7 +245,8 @@ __global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
     const float outscale = 1.0f / (dscale * cscale);
 
     load_plane(z_first);
-    store_plane();
+    split_plane();
+    write_plane();
     if (z_first + 1 < z_last) load_plane(z_first + 1);
     __syncthreads();
     // B fragments of chunk ch (hi and lo) into buffer set `buf`
@@ -280,6 +289,7 @@ __global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
             const int ch = u / Q, dzi = u % Q;
             if (dzi == 0 && ch + 1 < NCH) load_b(ch + 1, (ch + 1) & 1);
             if (u + 2 < S::NU) load_a(u + 2, (u + 2) % PF);
+            if (u == S::NU / 2 && zi + 1 < z_last) split_plane();   // plane zi + 1
             // keep the requests above this unit's MFMAs (the scheduler would sink them)
             __builtin_amdgcn_sched_barrier(0);
             const uint4 &ahi = ah[u % PF];
@@ -327,7 +337,7 @@ __global__ void __launch_bounds__(64 * NW) box_mfma_kernel(MfmaArgs a) {
         for (int t = 0; t < NT; ++t) acc[Q - 1][t] = floatx4{0.f, 0.f, 0.f, 0.f};
         __syncthreads();   // every wave is done with plane zi
         if (zi + 1 < z_last) {
-            store_plane();                              // plane zi + 1
+            write_plane();                              // plane zi + 1
             if (zi + 2 < z_last) load_plane(zi + 2);    // requested a whole plane ahead
         }
         __syncthreads();
