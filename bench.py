@@ -66,7 +66,7 @@ def parse():
                    "box4_fp16x3s|box3_bf16x3|wave|vti|copy|2DStarR2|2DStarR4|2DBoxR2|2DBoxR3|"
                    "3DStarR2|3DBoxR1|tti")
     p.add_argument("--skip", default="", help="comma list of extras to skip: "
-                   "split,table1,rtm,vti,tti,gradient,cpu,check")
+                   "config0,split,table1,rtm,vti,tti,gradient,cpu,check")
     p.add_argument("--collect", action="store_true",
                    help="run rocprofv3 (kernel trace, FETCH_SIZE, WRITE_SIZE) as child processes "
                         "over the headline kernels and a plain copy, and write profiles/")
@@ -248,7 +248,8 @@ def main():
         "rooflines": rooflines,
         "kernels": kernels,
     }
-    result["config0"] = bench_config0(torch, mms, synth, dev)
+    if "config0" not in skip:
+        result["config0"] = bench_config0(torch, mms, synth, dev)
     if "split" not in skip:
         result["split_mfma"] = bench_split(torch, mms, grid, x, c_box4, c_box3, dev)
     if "table1" not in skip:
@@ -968,7 +969,8 @@ def collect_counters(args):
 
     summary = {"kernels": {}, "commands": {}}
     # 1. kernel trace of the headline command
-    targs = ["--steps", "60", "--warmup", "40", "--skip", "split,table1,rtm,vti,tti,gradient,cpu,check"]
+    targs = ["--steps", "60", "--warmup", "40", "--skip",
+             "config0,split,table1,rtm,vti,tti,gradient,cpu,check"]
     d, cmd = prof("trace_headline", ["--kernel-trace", "--stats"], targs, 300)
     stats = find(d, "_kernel_stats.csv")
     summary["commands"]["trace_headline"] = cmd
