@@ -46,7 +46,8 @@ extern "C" {
 /* error codes */
 #define MMS_OK 0
 #define MMS_EINVAL (-1)       /* null pointer, bad layout, bad sizes, aliasing   */
-#define MMS_EUNSUPPORTED (-2) /* radius outside 1..4, unknown shape, split precision other than on a 3-D box */
+#define MMS_EUNSUPPORTED (-2) /* radius outside 1..4, unknown shape, split precision other than on a 3-D box,
+                                 an FP32 box over rows too long for its tile offsets */
 #define MMS_EHIP (-3)         /* HIP runtime or launch error (see mms_last_error)*/
 #define MMS_ENOMEM (-4)       /* reserved: no call of this version allocates      */
 #define MMS_EUNSTABLE (-5)    /* a reduction result reports NaN or Inf values     */
@@ -90,6 +91,8 @@ typedef struct mms_grid {
  * shapes; any of the four for the box.  The box MFMA variants recast each (dz, dy) pair of the sweep as
  * a banded Toeplitz product along x, the matrix-unit mapping of Sec. IV-A, with
  * the (2r+1)^2 one-dimensional stencils of the box decomposition of Sec. IV-C.
+ * An FP32 box of radius 2-4 addresses a tile of (32 + 2r + 1) rows with 32-bit
+ * offsets: a pitch sy with (33 + 2r) * sy >= 2^32 gives MMS_EUNSUPPORTED.
  */
 int mms_stencil_apply(const float *in, float *out, const mms_grid *g, int shape, int radius,
                       const float *coeffs, int ncoeffs, int precision, void *stream);

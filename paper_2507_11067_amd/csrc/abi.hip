@@ -73,6 +73,8 @@ int scratch_address(double **p) {
 }
 }  // namespace
 
+void set_last_error(const char *msg) { snprintf(g_last, sizeof g_last, "%s", msg); }
+
 int hip_fail(hipError_t e, const char *where) {
     snprintf(g_last, sizeof g_last, "%s: %s", where, hipGetErrorString(e));
     return MMS_EHIP;

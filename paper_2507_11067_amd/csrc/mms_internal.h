@@ -12,6 +12,8 @@ namespace mms {
 int hip_fail(hipError_t e, const char *where);
 // Checks hipGetLastError after a launch.
 int check_launch(const char *where);
+// Records a message for mms_last_error() (for errors that are not HIP's).
+void set_last_error(const char *msg);
 
 // Layout checks of the ABI (host side, before any HIP call).
 bool grid_ok(const mms_grid *g, int radius);
