@@ -253,3 +253,15 @@ def test_energy_noalloc_refuses_grids_beyond_its_scratch(L):
                                      None) == -1
     assert L.mms_wave_energy_noalloc(ctypes.byref(small), vp(0x100000), vp(0x800000),
                                      vp(0x2000004), None) == -1      # misaligned result pair
+
+
+def test_fp32_box_refuses_rows_too_long_for_tile_offsets(L):
+    """From radius 2 on the FP32 box addresses its plane tile with 32-bit offsets; a
+    pitch whose (33 + 2r) rows reach 2^32 elements is refused before any HIP call."""
+    sy = 2 ** 28                                  # 37 rows: 9.9e9 elements
+    g = grid(nx=4, ny=1, nz=1, sy=sy)
+    nbytes = 9 * g.sz * 4                         # (nz + 2H) planes
+    out = ctypes.c_void_p(0x10000 + nbytes)
+    for r in (2, 3, 4):
+        assert apply(L, g, shape=1, r=r, out=out) == -2, r
+        assert "32-bit" in L.mms_last_error().decode()
