@@ -377,6 +377,19 @@ def bench_rtm(torch, mms, synth, dev, n=400, nt=2000):
         if with_image:
             res["trace_max_abs"] = float(traces.abs().max().item())
             res[key]["image_sum"] = float(image.sum().item())
+    # context for the step's access mix (three fields read, one written): what a plain
+    # streaming op over four grids of the same padded size moves on this GPU, timed the
+    # same way (torch.addcmul reads three and writes one)
+    st = [grid.zeros(dev) for _ in range(4)]
+    for t in st[:3]:
+        t.uniform_(-1.0, 1.0)
+    sms = time_launches(torch, lambda: torch.addcmul(st[0], st[1], st[2], out=st[3]))
+    stream_gbs = 4.0 * st[0].numel() * 4 / (sms * 1e-3) / 1e9
+    del st
+    res["stream_3r1w_gbs"] = stream_gbs
+    res["no_image"]["frac_of_stream"] = res["no_image"]["gbs"] / stream_gbs
+    log(f"[bench] rtm: three-read one-write stream of the padded grid {stream_gbs:.0f} GB/s; "
+        f"the step (no image) at {res['no_image']['frac_of_stream']:.2f} of it (algorithmic bytes)")
     return res
 
 

@@ -139,7 +139,7 @@ struct TtiArgs {
     float c2w[5], d1[4];
     const float *pc, *qc, *dzp, *dzq;   // tiles
     const float *dzzp, *dzzq, *pp, *qp, *c2, *eps, *delta, *theta, *phi;  // own words
-    float c2s, sigma, alpha;
+    float c2s, sigma, alpha, inv_alpha;
     float *pn, *qn;
     float *traces;
     const float *src;
@@ -276,7 +276,10 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
         // x/y parts of L f and H1 f for both fields: [field][e].  Rows y+k and y-k are
         // taken together (they share the weights d_k and c_k); k runs as a loop so
         // that only one pair of rows per field is in registers at a time.
-        float sxx[2][4], syy[2][4], sxy[2][4], sxz[2][4], syz[2][4];
+        float sxx[2][4], syy[2][4], sxz[2][4], syz[2][4];
+        // Dy f over the 12-cell window of each field, summed over k; Dxy = Dx(Dy f)
+        // is taken once after the k loop
+        float dyw[2][12];
         auto window = [&](const float4 *row, float *w) {
             const float4 L = row[0], C = row[1], Rr = row[2];
             w[0] = L.x; w[1] = L.y; w[2] = L.z; w[3] = L.w;
@@ -303,10 +306,11 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
                 for (int j = 1; j <= R; ++j) s2 = fmaf(a.c2w[j], w[4 + e + j] + w[4 + e - j], s2);
                 sxx[fi][e] = s2;
                 syy[fi][e] = a.c2w[0] * w[4 + e];
-                sxy[fi][e] = 0.f;
                 sxz[fi][e] = dx1(wz, e);
                 syz[fi][e] = 0.f;
             }
+#pragma unroll
+            for (int i = 0; i < 12; ++i) dyw[fi][i] = 0.f;
         }
 #pragma unroll 1
         for (int k = 1; k <= R; ++k) {
@@ -315,18 +319,18 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
             for (int fi = 0; fi < 2; ++fi) {
                 const float4 *t = &tile[buf][fi][0][0] + ty * LW4 + tx;
                 const float4 *tz = &tile[buf][2 + fi][0][0] + ty * LW4 + tx;
-                float wu[12], wd[12], wdiff[12];
+                float wu[12], wd[12];
                 window(t + (R + k) * LW4, wu);
                 window(t + (R - k) * LW4, wd);
-                // Dx is linear: Dx(row y+k) - Dx(row y-k) = Dx(row y+k - row y-k), one x
-                // derivative per cell instead of two
+                // Dx and Dy commute: Dxy f = Dx(sum_k d_k (row y+k - row y-k)), so the
+                // rows' difference is summed over the window and differentiated in x
+                // once, after the loop
 #pragma unroll
-                for (int i = 0; i < 12; ++i) wdiff[i] = wu[i] - wd[i];
+                for (int i = 0; i < 12; ++i) dyw[fi][i] = fmaf(dk, wu[i] - wd[i], dyw[fi][i]);
                 const float4 zu = tz[(R + k) * LW4 + 1], zd = tz[(R - k) * LW4 + 1];
                 const float zuv[4] = {zu.x, zu.y, zu.z, zu.w}, zdv[4] = {zd.x, zd.y, zd.z, zd.w};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    sxy[fi][e] = fmaf(dk, dx1(wdiff, e), sxy[fi][e]);
                     syy[fi][e] = fmaf(ck, wu[4 + e] + wd[4 + e], syy[fi][e]);
                     syz[fi][e] = fmaf(dk, zuv[e] - zdv[e], syz[fi][e]);
                 }
@@ -338,8 +342,9 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 lxy[fi][e] = sxx[fi][e] + syy[fi][e];
-                h1[fi][e] = cf[0][e] * sxx[fi][e] + cf[1][e] * syy[fi][e] + cf[3][e] * sxy[fi][e] +
-                            cf[4][e] * syz[fi][e] + cf[5][e] * sxz[fi][e];
+                h1[fi][e] = cf[0][e] * sxx[fi][e] + cf[1][e] * syy[fi][e] +
+                            cf[3][e] * dx1(dyw[fi], e) + cf[4][e] * syz[fi][e] +
+                            cf[5][e] * sxz[fi][e];
             }
         // keep the loads below the derivative phase (register pressure): the next
         // plane's tiles are requested here, so their latency overlaps this plane's
@@ -366,9 +371,9 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
                 H2[fi] = (lxy[fi][e] + dzz) - H1[fi];
             }
             const float eps = comp(ow[5], e), del = comp(ow[6], e);
-            const float sg = a.sigma, al = a.alpha;
+            const float sg = a.sigma, al = a.alpha, ia = a.inv_alpha;   // ia = 1 / alpha
             const float accp = (1.f + 2.f * eps) * H2[0] + al * H1[1] + sg * (H1[0] - al * H1[1]);
-            const float accq = (1.f + 2.f * del) / al * H2[0] + H1[1] - sg * (H2[0] / al - H2[1]);
+            const float accq = (1.f + 2.f * del) * ia * H2[0] + H1[1] - sg * (H2[0] * ia - H2[1]);
             const float G = gz * gown[e];
             const float C2 = a.c2s * comp(ow[4], e);
             rp[e] = G * (2.0f * pcv[e] - G * comp(ow[2], e) + C2 * accp);
@@ -478,6 +483,7 @@ int launch_tti(const mms_wave *w, const mms_tti *t, int n, const float *pp, cons
     a.c2s = w->c2_scale;
     a.sigma = t->sigma;
     a.alpha = t->alpha;
+    a.inv_alpha = 1.0f / t->alpha;
     a.pn = pn + o;
     a.qn = qn + o;
     a.traces = w->traces ? w->traces + (int64_t)n * gd->ny * gd->nx : nullptr;
