@@ -210,7 +210,9 @@ int mms_vti_step(const mms_wave *w, int n, const float *a, const float *b, const
 typedef struct mms_tti {
     const float *eps, *delta;  /* Thomsen parameters, device grids (layout g)             */
     const float *theta, *phi;  /* tilt of the symmetry axis from z and its azimuth from x,  */
-                               /* radians, device grids (layout g)                          */
+                               /* radians, device grids (layout g); |angle| < 1600 (sine   */
+                               /* and cosine come from the transcendental unit, absolute   */
+                               /* error below 1e-6)                                         */
     float sigma;               /* v_sz^2 / v_pz^2 (0 gives the pure pseudo-acoustic pair)   */
     float alpha;               /* scale of q in the coupling, > 0                           */
     float d1[4];               /* first-derivative weights d_1..d_radius:                   */

@@ -30,33 +30,15 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float4 f4(float a) { return make_float4(a, a, a, a); }
 
-// sin and cos of an angle of moderate size (the tilt and azimuth fields, |x| up to
-// a few 2 pi): Cody-Waite reduction by pi/2 with a two-term split of pi/2, then the
-// Taylor polynomials of sin (to x^11) and cos (to x^12) on |r| <= pi/4, whose
-// truncation errors (< 1e-12) are far below FP32 rounding.  This keeps the
-// library's general sincosf, with its large-argument path, out of the kernel.
-__device__ __forceinline__ void small_sincos(float x, float *sn, float *cs) {
-    const float q = rintf(x * 0.636619772367581343f);   // x / (pi/2)
-    float r = fmaf(-q, 1.57079637050628662109375f, x);   // pi/2 rounded to FP32
-    r = fmaf(-q, -4.37113900630947659e-8f, r);           // pi/2 minus that
-    const float r2 = r * r;
-    // sin r = r (1 - r^2/3! + r^4/5! - ...), cos r = 1 - r^2/2! + r^4/4! - ...
-    float ps = -2.50521083854417188e-8f;                 // -1/11!
-    ps = fmaf(ps, r2, 2.75573192239858907e-6f);          //  1/9!
-    ps = fmaf(ps, r2, -1.98412698412698413e-4f);         // -1/7!
-    ps = fmaf(ps, r2, 8.33333333333333333e-3f);          //  1/5!
-    ps = fmaf(ps, r2, -1.66666666666666667e-1f);         // -1/3!
-    const float s = fmaf(ps * r2, r, r);
-    float pc = 2.08767569878680990e-9f;                  //  1/12!
-    pc = fmaf(pc, r2, -2.75573192239858907e-7f);         // -1/10!
-    pc = fmaf(pc, r2, 2.48015873015873016e-5f);          //  1/8!
-    pc = fmaf(pc, r2, -1.38888888888888889e-3f);         // -1/6!
-    pc = fmaf(pc, r2, 4.16666666666666667e-2f);          //  1/4!
-    pc = fmaf(pc, r2, -0.5f);                            // -1/2!
-    const float c = fmaf(pc, r2, 1.0f);
-    const int k = ((int)q) & 3;
-    *sn = k == 0 ? s : k == 1 ? c : k == 2 ? -s : -c;
-    *cs = k == 0 ? c : k == 1 ? -s : k == 2 ? -c : s;
+// sin and cos of an angle on the transcendental unit (v_sin_f32 / v_cos_f32 take the
+// argument in revolutions and are valid below 256 revolutions in magnitude).  Measured
+// on MI355X against FP64 over [-4 pi, 4 pi]: absolute error at most 9.2e-7, RMS 2.4e-7;
+// one instruction each where a reduction plus polynomials took about 25, which made
+// the eight evaluations per lane and plane 9 % of the kernel's time.
+__device__ __forceinline__ void angle_sincos(float x, float *sn, float *cs) {
+    const float t = x * 0.159154943091895336f;   // x / (2 pi)
+    *sn = __builtin_amdgcn_sinf(t);
+    *cs = __builtin_amdgcn_cosf(t);
 }
 
 // ------------------------------------------------------------------ pass 1
@@ -262,8 +244,8 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             float st, ct, sp, cp;
-            small_sincos(comp(th4, e), &st, &ct);
-            small_sincos(comp(ph4, e), &sp, &cp);
+            angle_sincos(comp(th4, e), &st, &ct);
+            angle_sincos(comp(ph4, e), &sp, &cp);
             const float nx_ = st * cp, ny_ = st * sp, nz_ = ct;
             cf[0][e] = nx_ * nx_;
             cf[1][e] = ny_ * ny_;
