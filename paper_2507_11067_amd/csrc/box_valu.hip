@@ -54,9 +54,10 @@ __device__ __forceinline__ void load_lds16(const float *src, float4 *dst) {
 // R: radius; TX x TY lanes, each with 4 x-cells of NYL rows; LDSW: weights in LDS
 // and the plane tile loaded straight into LDS (radius 2 on); ONEPATH: one plane
 // body with a per-dz test instead of a tested and an untested copy; DYU: dy loop
-// unrolled.
-template <int R, int TX, int TY, bool LDSW, int NYL, bool ONEPATH, bool DYU>
-__global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
+// unrolled; MINW: waves per SIMD the register allocation must leave room for.
+template <int R, int TX, int TY, bool LDSW, int NYL, bool ONEPATH, bool DYU, int MINW>
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(MINW)))
+box_valu_kernel(BoxArgs a) {
     constexpr int W = 2 * R + 1;
     constexpr int BX = 4 * TX;
     constexpr int BY = TY * NYL;              // NYL output rows per lane
@@ -274,9 +275,9 @@ __global__ void __launch_bounds__(TX *TY) box_valu_kernel(BoxArgs a) {
 //    by twice the outputs (radius 3: 109 -> 117);
 //  * radius 2 (128 VGPRs, 4 waves per SIMD): dy unrolled, two plane bodies, 314
 //    against 304 with one body;
-//  * radius 3: dy unrolled and one plane body, 125 (134 VGPRs, 3 waves per SIMD)
-//    against 119 with two bodies (151 VGPRs) and 117 with dy as a loop (101 VGPRs,
-//    4 waves per SIMD);
+//  * radius 3: dy unrolled and one plane body, held to 128 VGPRs for 4 waves per SIMD
+//    (32 bytes per lane spilled): 133 against 128 at 134 VGPRs and 3 waves, 119 with
+//    two bodies (151 VGPRs) and 117 with dy as a loop (101 VGPRs, 4 waves per SIMD);
 //  * radius 4: dy as a loop and one plane body (128 VGPRs, 4 waves per SIMD),
 //    67.6-68.9 against 66.3-67.2 for one row per lane; with two bodies, or dy
 //    unrolled, two rows need 170-220 VGPRs;
@@ -290,6 +291,7 @@ struct BoxShape {
     static constexpr int NYL = R >= 2 ? 2 : 1;
     static constexpr bool ONEPATH = R >= 3;
     static constexpr bool DYU = R == 2 || R == 3;
+    static constexpr int MINW = R == 3 ? 4 : 1;
 };
 
 template <int R>
@@ -329,7 +331,7 @@ int launch_r(const float *in, float *out, const mms_grid *gd, const float *coeff
     for (int i = 0; i < W * W * W; ++i) a.c[i] = coeffs[i];
     const int64_t nblk = (int64_t)g.ntx * g.nty * g.nzc;
     if (nblk > 0x7fffffff) return MMS_EINVAL;
-    hipLaunchKernelGGL((box_valu_kernel<R, TX, TY, LDSW, NYL, S::ONEPATH, S::DYU>),
+    hipLaunchKernelGGL((box_valu_kernel<R, TX, TY, LDSW, NYL, S::ONEPATH, S::DYU, S::MINW>),
                        dim3((unsigned)nblk), dim3(TX * TY), 0, s, a);
     return check_launch("box_valu_kernel");
 }
