@@ -589,7 +589,7 @@ def bench_gradient(torch, mms, synth, dev, n=256, nt=1000, K=50):
     # fixed m, x = two smooth random levels.  y = A x + the misfit residual scaled to the norm
     # of A x (gated, 1e-5 relative); y = the residual alone is also reported: x and y are then
     # unrelated, |<A x, y>| is a small fraction of |A x| |y| and the relative error is
-    # amplified by its inverse, so that case is gated on |lhs - rhs| / (|A x| |y|)
+    # amplified by its inverse, so that case is measured by |lhs - rhs| / (|A x| |y|)
     r = torch.empty_like(traces)
     mms.flat_misfit(traces.detach(), d_obs, resid=r)
     w = mms.Wave(grid, m.detach(), LAP, nt, (s.dt / s.h) ** 2, s.sponge_width, s.sponge_alpha,
