@@ -91,6 +91,30 @@ def test_star_nonzero_halo_and_wide_pitch(mms):
 
 
 @pytest.mark.parametrize("r", [1, 2, 3, 4])
+@pytest.mark.parametrize("shape,prec", [("box", "fp32"), ("box", "bf16x3"), ("box", "fp16x3s"),
+                                        ("star2d", "fp32"), ("box2d", "fp32")])
+def test_nonzero_halo_and_wide_pitch(mms, shape, prec, r):
+    """Halo cells are read as stored by every sweep kernel (the star has its own case above):
+    random values in an 8-cell halo, a row pitch wider than the rows need, and a ragged
+    interior (30 x 21 x 13) so that tiles end inside the halo."""
+    nx, ny, nz, H = 30, 21, 13, 8
+    grid = mms.Grid(nx, ny, nz, halo=H, sy=64)
+    rng = np.random.default_rng(50 + r)
+    x = rng.uniform(-1, 1, grid.shape).astype(np.float32)
+    w = 2 * r + 1
+    if shape == "box":
+        c, ref_fn = synth.box_coeffs(60 + r, r), oracle.box
+    elif shape == "box2d":
+        c, ref_fn = synth.box2d_coeffs(70 + r, r), oracle.box2d
+    else:
+        c, ref_fn = rng.uniform(-1, 1, (2, w)).astype(np.float32), oracle.star2d
+    got = run(mms, x, grid, shape, r, c, prec)
+    ref = ref_fn(x, nx, ny, nz, r, c, halo=H)
+    rmax, rrms = rel_errors(interior(got, grid), interior(ref, grid))
+    assert rmax <= TOL, (rmax, rrms)
+
+
+@pytest.mark.parametrize("r", [1, 2, 3, 4])
 @pytest.mark.parametrize("size", [(8, 8, 8), (17, 19, 23), (70, 33, 40), (3, 2, 5)],
                          ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3s"])
