@@ -85,6 +85,30 @@ def test_tti_step_parity(mms, dims):
     assert torch.count_nonzero(traces[:n]) == 0 and torch.count_nonzero(traces[n + 1:]) == 0
 
 
+def test_tti_step_reads_halo_as_stored(mms):
+    """Halo cells of p^n and q^n enter both passes as stored (Dz and Dzz over the z halo, the
+    x/y derivatives and the mixed ones over the x and y halos): random values in the whole
+    padded arrays of both fields at both levels; the outputs' halos are never written."""
+    nx, ny, nz = 37, 19, 11
+    nt, n = 8, 3
+    grid, c2, fields, f, src = medium(mms, nx, ny, nz, 130, nt)
+    rng = np.random.default_rng(137)
+    pp, pc, qp, qc = (rng.uniform(-1, 1, grid.shape).astype(np.float32) for _ in range(4))
+    w = mms.Wave(grid, T(c2), LAP, nt, 1.0, 4, 0.1, FACES, src, T(f))
+    t = gpu_tti(mms, grid, fields)
+    pn, qn = grid.zeros(DEV).fill_(7.0), grid.zeros(DEV).fill_(7.0)
+    w.tti_step(n, t, T(pp), T(pc), pn, T(qp), T(qc), qn)
+    torch.cuda.synchronize()
+    ow = oracle.Wave(nx, ny, nz, c2, LAP, src, f, nt, 4, 0.1, FACES)
+    rp, rq, _ = ow.tti_step(oracle_tti(ow, fields), n, pp, pc, qp, qc)
+    for name, got, ref in (("p", pn, rp), ("q", qn, rq)):
+        g = got.cpu().numpy()
+        rmax, rrms = rel_errors(interior(g, grid), interior(ref, grid))
+        assert rmax <= 1e-5, (name, rmax, rrms)
+        interior(g, grid)[...] = 7.0
+        assert np.all(g == 7.0)
+
+
 @pytest.mark.parametrize("radius", [1, 2, 3])
 def test_tti_step_parity_short_radius(mms, radius):
     nx, ny, nz = 45, 13, 17

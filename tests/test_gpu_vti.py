@@ -75,6 +75,29 @@ def test_vti_step_parity(mms, dims):
     assert torch.count_nonzero(traces[:n]) == 0 and torch.count_nonzero(traces[n + 1:]) == 0
 
 
+def test_vti_step_reads_halo_as_stored(mms):
+    """Halo cells of H^n (x and y neighbours) and V^n (z neighbours) enter the step as stored:
+    random values in the whole padded arrays of both fields at both levels; the outputs'
+    halos are never written."""
+    nx, ny, nz = 37, 19, 11
+    nt, n = 8, 3
+    grid, c2, a, b, f, src = medium(mms, nx, ny, nz, 30, nt)
+    rng = np.random.default_rng(33)
+    hp, hc, vp, vc = (rng.uniform(-1, 1, grid.shape).astype(np.float32) for _ in range(4))
+    w = mms.Wave(grid, T(c2), LAP, nt, 1.0, 4, 0.1, FACES, src, T(f))
+    hn, vn = grid.zeros(DEV).fill_(7.0), grid.zeros(DEV).fill_(7.0)
+    w.vti_step(n, T(a), T(b), T(hp), T(hc), hn, T(vp), T(vc), vn)
+    torch.cuda.synchronize()
+    rh, rv, _ = oracle.Wave(nx, ny, nz, c2, LAP, src, f, nt, 4, 0.1, FACES).vti_step(
+        n, a, b, hp, hc, vp, vc)
+    for got, ref in ((hn, rh), (vn, rv)):
+        g = got.cpu().numpy()
+        rmax, rrms = rel_errors(interior(g, grid), interior(ref, grid))
+        assert rmax <= 1e-5, (rmax, rrms)
+        interior(g, grid)[...] = 7.0
+        assert np.all(g == 7.0)
+
+
 @pytest.mark.parametrize("radius", [1, 2, 3])
 def test_vti_step_parity_short_radius(mms, radius):
     nx, ny, nz = 45, 13, 17

@@ -86,6 +86,29 @@ def test_forward_step_parity(mms, dims):
     assert abs(got[src[0] + 4, src[1] + 4, src[2] + 4]) > 0
 
 
+def test_forward_step_reads_halo_as_stored(mms):
+    """Halo cells of u^n enter the stencil as stored (the grid contract): random values in the
+    whole padded arrays of u^n and u^{n-1} (C2's halo stays zero, as the contract requires);
+    the output's halo is never written."""
+    nx, ny, nz = 30, 22, 18
+    nt, n = 10, 5
+    grid, c2, f, src, _ = setup_small(mms, nx, nt, 1, ny=ny, nz=nz)
+    rng = np.random.default_rng(9)
+    up = rng.uniform(-1, 1, grid.shape).astype(np.float32)
+    uc = rng.uniform(-1, 1, grid.shape).astype(np.float32)
+    w = gpu_wave(mms, grid, T(c2), T(f), src, nt, 4)
+    un = grid.zeros(DEV).fill_(7.0)
+    w.step(n, T(up), T(uc), un)
+    torch.cuda.synchronize()
+    ref, _ = oracle_wave(grid, c2, f, src, nt, 4).step(n, up, uc)
+    got = un.cpu().numpy()
+    rmax, rrms = rel_errors(interior(got, grid), interior(ref, grid))
+    assert rmax <= 1e-5, (rmax, rrms)
+    halo = got.copy()
+    interior(halo, grid)[...] = 7.0
+    assert np.all(halo == 7.0)
+
+
 @pytest.mark.parametrize("n_step,dims", [(0, (30, 22, 18)), (1, (30, 22, 18)), (6, (30, 22, 18)),
                                          (6, (300, 9, 13))],
                          ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else str(v))
