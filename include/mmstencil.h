@@ -233,7 +233,9 @@ typedef struct mms_tti {
  * first-derivative stencil t->d1 along the two axes (the composition of one-dimensional
  * stencils of Sec. IV-G).  traces[n] = p^n(z = 0); the image is not used.  Grid cells are read
  * as stored, halo included.  p_next may equal p_prev and q_next may equal q_prev; no other
- * pair of arguments (work included) may overlap.
+ * pair of arguments (work included) may overlap.  The second pass addresses tiles of
+ * (8 + 2r + 1) rows with 32-bit offsets: a pitch sy with (9 + 2r) * sy >= 2^32 gives
+ * MMS_EUNSUPPORTED before either pass runs.
  */
 int mms_tti_step(const mms_wave *w, const mms_tti *t, int n, const float *p_prev,
                  const float *p_cur, float *p_next, const float *q_prev, const float *q_cur,

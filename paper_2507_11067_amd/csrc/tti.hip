@@ -15,9 +15,9 @@
 //    a workspace of four grids.  Each plane of the padded array is contiguous,
 //    so a lane owns one 16-byte word of it and the loads are fully coalesced.
 //  * pass 2 (x and y): per plane, the tiles of p, q, Dz p and Dz q with r rows
-//    and 4 cells of halo are staged in a double-buffered LDS tile (the next
-//    plane's tiles are requested after the current plane's derivatives, so that
-//    no registers stay reserved for them across that phase); Dxx, Dyy and Dxy = Dx(Dy f) come from the p / q tiles, Dxz =
+//    and 4 cells of halo go from memory straight into a double-buffered LDS tile
+//    (requested after the current plane's derivatives, with no staging
+//    registers); Dxx, Dyy and Dxy = Dx(Dy f) come from the p / q tiles, Dxz =
 //    Dx(Dz f) and Dyz = Dy(Dz f) from the Dz tiles; the direction cosines come
 //    from theta / phi per cell; the update is fused with the sponge, source and
 //    receivers; outputs are written with streaming stores.
@@ -116,6 +116,12 @@ __global__ void __launch_bounds__(256) tti_dz_kernel(DzArgs a) {
 }
 
 // ------------------------------------------------------------------ pass 2
+// One 16-byte word per lane from memory straight into LDS: lane l's word lands at
+// dst + l (dst the same for the whole wave); completion is counted by vmcnt.
+__device__ __forceinline__ void load_lds16(const float *src, float4 *dst) {
+    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+}
+
 struct TtiArgs {
     Geom g;
     float c2w[5], d1[4];
@@ -139,8 +145,6 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
     constexpr int BY = TY;
     constexpr int LW4 = TX + 2, LH = BY + 2 * R;
     constexpr int NT = TX * TY;
-    constexpr int NH = 2 * R * LW4 + 2 * BY;
-    constexpr int NHK = (NH + NT - 1) / NT;
     __shared__ float4 tile[2][NTILE][LH][LW4];
 
     const Geom &g = a.g;
@@ -173,58 +177,36 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) gown[e] = gy * gaxis(x0 + e, g.nx, W, sa, a.faces & 1, a.faces & 2);
     }
-    int64_t h_off[NHK];
-    int h_lds[NHK];
-    bool h_ok[NHK], h_on[NHK];  // h_on: item k is one of this tile's halo words
+    // tile word i -> (row i / LW4, col i % LW4) from the tile origin (row yt - R, column
+    // xt - 4), loaded straight into LDS; words outside this tile's lw columns or outside the
+    // array are read from the origin instead (they are never used)
+    constexpr int NL = LH * LW4;
+    constexpr int NLK = (NL + NT - 1) / NT;
+    uint32_t d_off[NLK];
 #pragma unroll
-    for (int k = 0; k < NHK; ++k) {
+    for (int k = 0; k < NLK; ++k) {
         const int i = tid + k * NT;
-        int row, lrow, col4, x;
-        if (i < 2 * R * lw) {
-            const int hr = i / lw, hc = i % lw;
-            row = hr < R ? yt - R + hr : yt + BY + (hr - R);
-            lrow = hr < R ? hr : hr + BY;
-            col4 = hc;
-            x = xt - 4 + 4 * hc;
-        } else {
-            const int j = i - 2 * R * lw;
-            row = yt + j / 2;
-            lrow = R + j / 2;
-            col4 = (j & 1) ? txa + 1 : 0;
-            x = (j & 1) ? xt + bxa : xt - 4;
-        }
-        h_on[k] = i < 2 * R * lw + 2 * BY;
-        h_ok[k] = h_on[k] && (row < ylim) && (x <= nx4);
-        h_off[k] = (int64_t)row * sy + x;
-        h_lds[k] = lrow * LW4 + col4;
+        const int row = i / LW4, col = i % LW4;
+        const bool ok = (i < NL) && (col < lw) && (yt - R + row < ylim) && (xt - 4 + 4 * col <= nx4);
+        d_off[k] = ok ? (uint32_t)row * (uint32_t)sy + 4u * (uint32_t)col : 0u;
     }
     const float *tsrc[NTILE] = {a.pc, a.qc, a.dzp, a.dzq};
     // point-wise operands (theta and phi, the last two, are loaded separately)
     const float *osrc[NOWN] = {a.dzzp, a.dzzq, a.pp, a.qp, a.c2, a.eps, a.delta, a.theta, a.phi};
-    auto load_tiles = [&](int z, float4 (*tw)[1 + NHK]) {
-        const int64_t zo = (int64_t)z * sz;
+    const int wave_base = __builtin_amdgcn_readfirstlane(tid & ~63);
+    auto load_tiles = [&](int z, int buf) {
+        const int64_t zo = (int64_t)z * sz + (int64_t)(yt - R) * sy + (xt - 4);
 #pragma unroll
         for (int f = 0; f < NTILE; ++f) {
-            tw[f][0] = select_load(tsrc[f] + zo + own_off, own_ok, a.c2);
+            float4 *dst = &tile[buf][f][0][0] + wave_base;
 #pragma unroll
-            for (int k = 0; k < NHK; ++k)
-                tw[f][1 + k] = select_load(tsrc[f] + zo + h_off[k], h_ok[k], a.c2);
-        }
-    };
-    auto tile_store = [&](int buf, float4 (*tw)[1 + NHK]) {
-#pragma unroll
-        for (int f = 0; f < NTILE; ++f) {
-            float4 *t = &tile[buf][f][0][0];
-            if (lane_on) t[(R + ty) * LW4 + tx + 1] = tw[f][0];
-#pragma unroll
-            for (int k = 0; k < NHK; ++k)
-                if (h_on[k]) t[h_lds[k]] = tw[f][1 + k];
+            for (int k = 0; k < NLK; ++k)
+                if (tid + k * NT < NL) load_lds16(tsrc[f] + zo + d_off[k], dst + k * NT);
         }
     };
 
-    float4 tw[NTILE][1 + NHK];
-    load_tiles(zb, tw);
-    tile_store(0, tw);
+    load_tiles(zb, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
     const float srcv = a.src ? *a.src : 0.f;
@@ -332,14 +314,15 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
         // plane's tiles are requested here, so their latency overlaps this plane's
         // point-wise loads, update and stores
         __builtin_amdgcn_sched_barrier(0);
-        if (more) load_tiles(z + 1, tw);
+        // the centre words of p and q are read before the next plane's tiles are requested
+        const float4 *ctrp = &tile[buf][0][0][0] + (R + ty) * LW4 + tx + 1;
+        const float4 *ctrq = &tile[buf][1][0][0] + (R + ty) * LW4 + tx + 1;
+        const float4 pc4 = *ctrp, qc4 = *ctrq;
+        if (more) load_tiles(z + 1, buf ^ 1);
         float4 ow[NOWN];
 #pragma unroll
         for (int f = 0; f < NOWN - 2; ++f) ow[f] = select_load(osrc[f] + zo + own_off, own_ok, a.c2);
 
-        const float4 *ctrp = &tile[buf][0][0][0] + (R + ty) * LW4 + tx + 1;
-        const float4 *ctrq = &tile[buf][1][0][0] + (R + ty) * LW4 + tx + 1;
-        const float4 pc4 = *ctrp, qc4 = *ctrq;
         const float pcv[4] = {pc4.x, pc4.y, pc4.z, pc4.w}, qcv[4] = {qc4.x, qc4.y, qc4.z, qc4.w};
         const float gz = gaxis(z, g.nz, W, sa, zlo, zhi);
         float rp[4], rq[4];
@@ -369,6 +352,11 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
                     rq[e] += srcv;
                 }
         }
+        // the next plane's tiles are in LDS once this lane's requests are done; the barrier
+        // publishes every lane's words and ends all reads of this plane; the output stores
+        // come after it, so that the wait does not cover them
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
         if (lane_on && y < g.ny && x0 < g.nx) {
             float *pp_ = a.pn + (int64_t)z * sz + own_off;
             float *qq_ = a.qn + (int64_t)z * sz + own_off;
@@ -392,8 +380,6 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
                     if (x0 + e < g.nx) pt[e] = pcv[e];
             }
         }
-        if (more) tile_store(buf ^ 1, tw);
-        __syncthreads();
     }
 }
 
@@ -406,6 +392,12 @@ int launch_tti(const mms_wave *w, const mms_tti *t, int n, const float *pp, cons
                float *pn, const float *qp, const float *qc, float *qn, hipStream_t s) {
     const mms_grid *gd = &w->g;
     const int64_t o = (int64_t)gd->halo * (gd->sz + gd->sy + 1);
+    // pass 2 addresses its plane tiles with 32-bit offsets from the tile origin; checked
+    // before either pass is launched
+    if ((int64_t)(TTY + 2 * R + 1) * gd->sy >= ((int64_t)1 << 32)) {
+        set_last_error("TTI step: grid rows too long for 32-bit tile offsets");
+        return MMS_EUNSUPPORTED;
+    }
     const int64_t L = grid_elems(gd);
     float *dzp = t->work, *dzq = t->work + L, *dzzp = t->work + 2 * L, *dzzq = t->work + 3 * L;
     // pass 1 over every word of the interior planes (rows of the y halo included)

@@ -265,3 +265,21 @@ def test_fp32_box_refuses_rows_too_long_for_tile_offsets(L):
     for r in (2, 3, 4):
         assert apply(L, g, shape=1, r=r, out=out) == -2, r
         assert "32-bit" in L.mms_last_error().decode()
+
+
+def test_tti_refuses_rows_too_long_for_tile_offsets(L):
+    """TTI pass 2 addresses its plane tiles with 32-bit offsets; a pitch whose 17 rows reach
+    2^32 elements is refused before either pass is launched (no HIP call)."""
+    from paper_2507_11067_amd._lib import MmsTti, MmsWave
+    g = grid(nx=4, ny=1, nz=1, sy=2 ** 28)
+    nbytes = 9 * g.sz * 4
+    step = 4 * nbytes + (1 << 20)
+    ptr = [ctypes.c_void_p(0x10000 + k * step) for k in range(12)]
+    lap = (ctypes.c_float * 5)(-2.8, 1.6, -0.2, 0.025, -0.0018)
+    w = MmsWave(g, 4, lap, ptr[0], 1.0, 0, 0.0, 0, 10, 0, 0, 0, None, None, None)
+    d1 = (ctypes.c_float * 4)(0.8, -0.2, 0.038, -0.0036)
+    t = MmsTti(ptr[1], ptr[2], ptr[3], ptr[4], 0.1, 1.0, d1, ptr[5])
+    rc = L.mms_tti_step(ctypes.byref(w), ctypes.byref(t), 1, ptr[6], ptr[7], ptr[8], ptr[9],
+                        ptr[10], ptr[11], None)
+    assert rc == -2, rc
+    assert "32-bit" in L.mms_last_error().decode()
