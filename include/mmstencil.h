@@ -199,6 +199,8 @@ int mms_wave_adjoint(const mms_wave *w, int n_hi, int n_lo, float *const *lams,
  * w->lap; C2, G, the source and dt as in mms_wave_step; traces[n] = H^n(z = 0); the
  * image is not used.  h_next may equal h_prev and v_next may equal v_prev; neither may
  * overlap h_cur or v_cur.
+ *  The H tile of (8 + 2r + 1) rows is addressed with 32-bit offsets: a pitch sy with
+ * (9 + 2r) * sy >= 2^32 gives MMS_EUNSUPPORTED.
  */
 int mms_vti_step(const mms_wave *w, int n, const float *a, const float *b, const float *h_prev,
                  const float *h_cur, float *h_next, const float *v_prev, const float *v_cur,

@@ -8,7 +8,8 @@
 // needs z neighbours, so (following the paper's decomposition of complex kernels
 // into one-dimensional stencils on small blocks, Sec. IV-G):
 //  * H travels through a double-buffered LDS tile (x/y halo), requested one plane
-//    ahead together with the neighbouring tiles;
+//    ahead straight from memory into LDS (no staging registers), together with the
+//    neighbouring tiles;
 //  * V travels through a register queue of 2r+1 planes (z terms only);
 //  * the five point-wise operands (H^{n-1}, V^{n-1}, C2, a, b) are requested one
 //    plane ahead; both outputs are written with streaming stores.
@@ -35,15 +36,24 @@ struct VtiArgs {
     int faces;
 };
 
+// One 16-byte word per lane from memory straight into LDS: lane l's word lands at
+// dst + l (dst the same for the whole wave); completion is counted by vmcnt.
+__device__ __forceinline__ void load_lds16(const float *src, float4 *dst) {
+    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+}
+
 template <int R, int TX, int TY>
 __global__ void __launch_bounds__(TX *TY) vti_kernel(VtiArgs a) {
     constexpr int Q = 2 * R + 1;
     constexpr int BY = TY;
     constexpr int LW4 = TX + 2, LH = BY + 2 * R;
     constexpr int NT = TX * TY;
-    constexpr int NH = 2 * R * LW4 + 2 * BY;
-    constexpr int NHK = (NH + NT - 1) / NT;
-    __shared__ float4 tile[2][LH][LW4];
+    constexpr int NL = LH * LW4;              // words of the H tile, row-major
+    constexpr int NLK = (NL + NT - 1) / NT;
+    // two arrays, each step's buffer fixed at compile time (phases in pairs), so that the
+    // compiler does not wait on the direct loads before the current plane's reads
+    __shared__ float4 tile0[NL];
+    __shared__ float4 tile1[NL];
 
     const Geom &g = a.g;
     int b = mms_xcd_remap(blockIdx.x, gridDim.x);
@@ -75,40 +85,26 @@ __global__ void __launch_bounds__(TX *TY) vti_kernel(VtiArgs a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) gown[e] = gy * gaxis(x0 + e, g.nx, W, sa, a.faces & 1, a.faces & 2);
     }
-    int64_t h_off[NHK];
-    int h_lds[NHK];
-    bool h_ok[NHK], h_on[NHK];  // h_on: item k is one of this tile's halo words
-#pragma unroll
-    for (int k = 0; k < NHK; ++k) {
-        const int i = tid + k * NT;
-        int row, lrow, col4, x;
-        if (i < 2 * R * lw) {
-            const int hr = i / lw, hc = i % lw;
-            row = hr < R ? yt - R + hr : yt + BY + (hr - R);
-            lrow = hr < R ? hr : hr + BY;
-            col4 = hc;
-            x = xt - 4 + 4 * hc;
-        } else {
-            const int j = i - 2 * R * lw;
-            row = yt + j / 2;
-            lrow = R + j / 2;
-            col4 = (j & 1) ? txa + 1 : 0;
-            x = (j & 1) ? xt + bxa : xt - 4;
-        }
-        h_on[k] = i < 2 * R * lw + 2 * BY;
-        h_ok[k] = h_on[k] && (row < ylim) && (x <= nx4);
-        h_off[k] = (int64_t)row * sy + x;
-        h_lds[k] = lrow * LW4 + col4;
-    }
     auto ld = [&](const float *base, int z, int64_t off, bool ok) -> float4 {
         return guarded_load(base + (int64_t)z * sz + off, ok, a.c2);
     };
-    auto tile_store = [&](int buf, const float4 &own, const float4 *halo) {
-        float4 *t = &tile[buf][0][0];
-        if (lane_on) t[(R + ty) * LW4 + tx + 1] = own;
+    // H tile word i -> (row i / LW4, col i % LW4) from the tile origin (row yt - R, column
+    // xt - 4); words outside this tile's lw columns or outside the array are read from the
+    // origin instead (never used)
+    uint32_t d_off[NLK];
 #pragma unroll
-        for (int k = 0; k < NHK; ++k)
-            if (h_on[k]) t[h_lds[k]] = halo[k];
+    for (int k = 0; k < NLK; ++k) {
+        const int i = tid + k * NT;
+        const int row = i / LW4, col = i % LW4;
+        const bool ok = (i < NL) && (col < lw) && (yt - R + row < ylim) && (xt - 4 + 4 * col <= nx4);
+        d_off[k] = ok ? (uint32_t)row * (uint32_t)sy + 4u * (uint32_t)col : 0u;
+    }
+    const int wave_base = __builtin_amdgcn_readfirstlane(tid & ~63);
+    auto load_tile = [&](int z, float4 *t) {
+        const float *p = a.hc + (int64_t)z * sz + (int64_t)(yt - R) * sy + (xt - 4);
+#pragma unroll
+        for (int k = 0; k < NLK; ++k)
+            if (tid + k * NT < NL) load_lds16(p + d_off[k], t + wave_base + k * NT);
     };
 
     // point-wise operands of a plane: H^{n-1}, V^{n-1}, C2, a, b
@@ -126,37 +122,33 @@ __global__ void __launch_bounds__(TX *TY) vti_kernel(VtiArgs a) {
     };
 
     float4 q[Q];          // V at planes z-R .. z+R
-    float4 hreg[NHK];
 #pragma unroll
     for (int i = 0; i < Q; ++i) q[i] = ld(a.vc, zb - R + i, own_off, own_ok);
-    {
-        const float4 own = ld(a.hc, zb, own_off, own_ok);
-#pragma unroll
-        for (int k = 0; k < NHK; ++k) hreg[k] = ld(a.hc, zb, h_off[k], h_ok[k]);
-        tile_store(0, own, hreg);
-    }
+    load_tile(zb, tile0);
     Pw pw = load_pw(zb);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
 
     const float *c = a.c;
     const float srcv = a.src ? *a.src : 0.f;
     const bool zlo = a.faces & 16, zhi = a.faces & 32;
-    int buf = 0;
+    // 2Q phases per round: the queue slot (ph mod Q) and the tile buffer (ph mod 2) are both
+    // compile-time indices
     for (int z = zb; z < ze;) {
 #pragma unroll
-        for (int ph = 0; ph < Q; ++ph) {
+        for (int ph = 0; ph < 2 * Q; ++ph) {
             if (z < ze) {
                 const bool more = z + 1 < ze;
-                float4 nq = q[ph], nown = make_float4(0.f, 0.f, 0.f, 0.f);
+                float4 *cur = (ph & 1) ? tile1 : tile0;
+                float4 *nxt = (ph & 1) ? tile0 : tile1;
+                float4 nq = q[ph % Q];
                 Pw npw = pw;
                 if (more) {
                     nq = ld(a.vc, z + R + 1, own_off, own_ok);
-                    nown = ld(a.hc, z + 1, own_off, own_ok);
-#pragma unroll
-                    for (int k = 0; k < NHK; ++k) hreg[k] = ld(a.hc, z + 1, h_off[k], h_ok[k]);
+                    load_tile(z + 1, nxt);
                     npw = load_pw(z + 1);
                 }
-                const float4 *t = &tile[buf][0][0];
+                const float4 *t = cur;
                 const float4 hc4 = t[(R + ty) * LW4 + tx + 1];
                 const float4 L = t[(R + ty) * LW4 + tx];
                 const float4 Rr = t[(R + ty) * LW4 + tx + 2];
@@ -167,7 +159,7 @@ __global__ void __launch_bounds__(TX *TY) vti_kernel(VtiArgs a) {
                 for (int k = -R; k <= R; ++k) {
                     const float ck = c[R + k];
                     const float4 vy = k == 0 ? hc4 : t[(R + ty + k) * LW4 + tx + 1];
-                    const float4 vz = q[(ph + R + k + Q) % Q];
+                    const float4 vz = q[(ph % Q + R + k + Q) % Q];
                     const float yv[4] = {vy.x, vy.y, vy.z, vy.w};
                     const float zv[4] = {vz.x, vz.y, vz.z, vz.w};
 #pragma unroll
@@ -177,7 +169,7 @@ __global__ void __launch_bounds__(TX *TY) vti_kernel(VtiArgs a) {
                     }
                 }
                 const float gz = gaxis(z, g.nz, W, sa, zlo, zhi);
-                const float4 vc4 = q[(ph + R) % Q];
+                const float4 vc4 = q[(ph % Q + R) % Q];
                 const float hcv[4] = {hc4.x, hc4.y, hc4.z, hc4.w};
                 const float vcv[4] = {vc4.x, vc4.y, vc4.z, vc4.w};
                 const float hpv[4] = {pw.hp.x, pw.hp.y, pw.hp.z, pw.hp.w};
@@ -202,6 +194,11 @@ __global__ void __launch_bounds__(TX *TY) vti_kernel(VtiArgs a) {
                             rv[e] += srcv;
                         }
                 }
+                // the next H tile is in LDS once this lane's requests are done; the barrier
+                // publishes every lane's words and ends all reads of this plane; the output
+                // stores come after it, so that the wait does not cover them
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
                 if (lane_on && y < g.ny && x0 < g.nx) {
                     float *ph_ = a.hn + (int64_t)z * sz + own_off;
                     float *pv_ = a.vn + (int64_t)z * sz + own_off;
@@ -226,12 +223,9 @@ __global__ void __launch_bounds__(TX *TY) vti_kernel(VtiArgs a) {
                     }
                 }
                 if (more) {
-                    tile_store(buf ^ 1, nown, hreg);
-                    q[ph] = nq;
+                    q[ph % Q] = nq;
                     pw = npw;
                 }
-                __syncthreads();
-                buf ^= 1;
                 ++z;
             }
         }
@@ -254,6 +248,11 @@ int vti_step(const mms_wave *w, int n, const float *fa, const float *fb, const f
     g.nz = (int)gd->nz;
     g.sy = gd->sy;
     g.sz = gd->sz;
+    // the H tile is addressed with 32-bit offsets from its origin
+    if ((int64_t)(VTY + 2 * w->radius + 1) * g.sy >= ((int64_t)1 << 32)) {
+        set_last_error("VTI step: grid rows too long for 32-bit tile offsets");
+        return MMS_EUNSUPPORTED;
+    }
     g.txa = balanced_tile_words(g.nx, VTX, &g.ntx);
     g.nty = (g.ny + VTY - 1) / VTY;
     // one 512-thread block per CU (VGPR-bound), 256 CUs; the V queue fill costs

@@ -283,3 +283,19 @@ def test_tti_refuses_rows_too_long_for_tile_offsets(L):
                         ptr[10], ptr[11], None)
     assert rc == -2, rc
     assert "32-bit" in L.mms_last_error().decode()
+
+
+def test_vti_refuses_rows_too_long_for_tile_offsets(L):
+    """The VTI step addresses its H tile with 32-bit offsets; a pitch whose 17 rows reach
+    2^32 elements is refused before the kernel is launched (no HIP call)."""
+    from paper_2507_11067_amd._lib import MmsWave
+    g = grid(nx=4, ny=1, nz=1, sy=2 ** 28)
+    nbytes = 9 * g.sz * 4
+    step = 4 * nbytes + (1 << 20)
+    ptr = [ctypes.c_void_p(0x10000 + k * step) for k in range(9)]
+    lap = (ctypes.c_float * 5)(-2.8, 1.6, -0.2, 0.025, -0.0018)
+    w = MmsWave(g, 4, lap, ptr[0], 1.0, 0, 0.0, 0, 10, 0, 0, 0, None, None, None)
+    rc = L.mms_vti_step(ctypes.byref(w), 1, ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6],
+                        ptr[7], ptr[8], None)
+    assert rc == -2, rc
+    assert "32-bit" in L.mms_last_error().decode()
