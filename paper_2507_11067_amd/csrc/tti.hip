@@ -218,6 +218,11 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
         // direction cosines of this plane's cells
         const float4 th4 = select_load(a.theta + zo + own_off, own_ok, a.c2);
         const float4 ph4 = select_load(a.phi + zo + own_off, own_ok, a.c2);
+        // the other point-wise operands are requested here, so that the derivative phase
+        // covers their latency (they are used only in the update)
+        float4 ow[NOWN];
+#pragma unroll
+        for (int f = 0; f < NOWN - 2; ++f) ow[f] = select_load(osrc[f] + zo + own_off, own_ok, a.c2);
         auto comp = [](const float4 &v, int e) {
             return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
         };
@@ -310,18 +315,15 @@ __global__ void __launch_bounds__(TX *TY) tti_kernel(TtiArgs a) {
                             cf[3][e] * dx1(dyw[fi], e) + cf[4][e] * syz[fi][e] +
                             cf[5][e] * sxz[fi][e];
             }
-        // keep the loads below the derivative phase (register pressure): the next
-        // plane's tiles are requested here, so their latency overlaps this plane's
-        // point-wise loads, update and stores
+        // the next plane's tiles are requested after the last reads of this plane's tiles
+        // (issued earlier, the compiler waits on them inside the k loop), so their latency
+        // overlaps this plane's update and stores
         __builtin_amdgcn_sched_barrier(0);
         // the centre words of p and q are read before the next plane's tiles are requested
         const float4 *ctrp = &tile[buf][0][0][0] + (R + ty) * LW4 + tx + 1;
         const float4 *ctrq = &tile[buf][1][0][0] + (R + ty) * LW4 + tx + 1;
         const float4 pc4 = *ctrp, qc4 = *ctrq;
         if (more) load_tiles(z + 1, buf ^ 1);
-        float4 ow[NOWN];
-#pragma unroll
-        for (int f = 0; f < NOWN - 2; ++f) ow[f] = select_load(osrc[f] + zo + own_off, own_ok, a.c2);
 
         const float pcv[4] = {pc4.x, pc4.y, pc4.z, pc4.w}, qcv[4] = {qc4.x, qc4.y, qc4.z, qc4.w};
         const float gz = gaxis(z, g.nz, W, sa, zlo, zhi);
