@@ -299,3 +299,24 @@ def test_vti_refuses_rows_too_long_for_tile_offsets(L):
                         ptr[7], ptr[8], None)
     assert rc == -2, rc
     assert "32-bit" in L.mms_last_error().decode()
+
+
+@pytest.mark.parametrize("empty", [dict(nx=0), dict(ny=0), dict(nz=0)], ids=["nx0", "ny0", "nz0"])
+def test_steps_on_empty_grids_return_before_any_launch(L, empty):
+    """The acoustic, adjoint, VTI and TTI steps on a grid with no interior cells validate
+    their arguments and return MMS_OK without a HIP call (the pointers are never read)."""
+    from paper_2507_11067_amd._lib import MmsTti, MmsWave
+    g = grid(**empty)
+    step = 4 * g.sz * (g.nz + 2 * g.halo) * 4 + (1 << 20)
+    ptr = [ctypes.c_void_p(0x10000 + k * step) for k in range(16)]
+    lap = (ctypes.c_float * 5)(-2.8, 1.6, -0.2, 0.025, -0.0018)
+    w = MmsWave(g, 4, lap, ptr[0], 1.0, 0, 0.0, 0, 10, 0, 0, 0, None, None, None)
+    assert L.mms_wave_step(ctypes.byref(w), 1, ptr[1], ptr[2], ptr[3], None) == 0
+    assert L.mms_wave_adjoint_step(ctypes.byref(w), 3, ptr[1], ptr[2], ptr[3], None, None, None,
+                                   None) == 0
+    assert L.mms_vti_step(ctypes.byref(w), 1, ptr[1], ptr[2], ptr[3], ptr[4], ptr[5], ptr[6],
+                          ptr[7], ptr[8], None) == 0
+    d1 = (ctypes.c_float * 4)(0.8, -0.2, 0.038, -0.0036)
+    t = MmsTti(ptr[9], ptr[10], ptr[11], ptr[12], 0.1, 1.0, d1, ptr[13])
+    assert L.mms_tti_step(ctypes.byref(w), ctypes.byref(t), 1, ptr[1], ptr[2], ptr[3], ptr[4],
+                          ptr[5], ptr[6], None) == 0
