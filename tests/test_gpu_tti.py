@@ -55,7 +55,8 @@ def oracle_tti(ow, fields, sigma=SIGMA, alpha=1.0, d1=D1):
     return ow.tti(*fields, sigma, alpha, d1)
 
 
-@pytest.mark.parametrize("dims", [(20, 20, 20), (37, 19, 11), (300, 10, 21)],
+@pytest.mark.parametrize("dims", [(20, 20, 20), (37, 19, 11), (300, 10, 21), (248, 6, 9),
+                                  (256, 5, 7)],
                          ids=lambda d: "x".join(map(str, d)))
 def test_tti_step_parity(mms, dims):
     nx, ny, nz = dims
