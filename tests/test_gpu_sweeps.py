@@ -35,10 +35,13 @@ def run(mms, x_np, grid, shape, r, c, prec="fp32", out_fill=0.0):
 
 
 SIZES = [(8, 8, 8), (17, 19, 23), (5, 3, 2), (1, 1, 1), (64, 64, 64), (133, 37, 20)]
+# grids of at most 2^20 points (all of SIZES) take the star's direct small-grid kernel;
+# these larger ragged ones take the z-marching kernel
+STAR_SIZES = SIZES + [(133, 100, 80), (70, 130, 150)]
 
 
 @pytest.mark.parametrize("r", [1, 2, 3, 4])
-@pytest.mark.parametrize("size", SIZES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("size", STAR_SIZES, ids=lambda s: "x".join(map(str, s)))
 def test_star_parity(mms, r, size):
     nx, ny, nz = size
     grid = mms.Grid(nx, ny, nz)
@@ -77,10 +80,14 @@ def test_star_laplacian_64_config0(mms):
     assert rmax <= TOL
 
 
-def test_star_nonzero_halo_and_wide_pitch(mms):
-    """Halo cells are read as stored; a wider row pitch and an 8-cell halo are honoured."""
-    nx, ny, nz, H = 30, 21, 13, 8
-    grid = mms.Grid(nx, ny, nz, halo=H, sy=64)
+@pytest.mark.parametrize("dims", [(30, 21, 13, 64), (120, 100, 90, 160)],
+                         ids=["direct-30x21x13", "marching-120x100x90"])
+def test_star_nonzero_halo_and_wide_pitch(mms, dims):
+    """Halo cells are read as stored; a wider row pitch and an 8-cell halo are honoured (by the
+    small-grid kernel and by the z-marching one)."""
+    nx, ny, nz, sy = dims
+    H = 8
+    grid = mms.Grid(nx, ny, nz, halo=H, sy=sy)
     rng = np.random.default_rng(5)
     x = rng.uniform(-1, 1, grid.shape).astype(np.float32)
     c = synth.star_coeffs_random(6, 4)
