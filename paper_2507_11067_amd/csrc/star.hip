@@ -228,6 +228,7 @@ __global__ void __launch_bounds__(256) star_direct_kernel(StarArgs a, int64_t nw
     // roundup4(nx) + 2H); rows and planes within r of the interior lie in the halo
     const float *p = g.in0 + (int64_t)z * g.sz + (int64_t)y * g.sy + x0;
     auto ld = [](const float *q) { return *reinterpret_cast<const float4 *>(q); };
+    auto at = [](const float4 &v, int e) { return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w; };
     const float4 L = ld(p - 4), C = ld(p), Rr = ld(p + 4);
     const float w[12] = {L.x, L.y, L.z, L.w, C.x, C.y, C.z, C.w, Rr.x, Rr.y, Rr.z, Rr.w};
     float4 yu[R], yd[R], zu[R], zd[R];
@@ -245,8 +246,8 @@ __global__ void __launch_bounds__(256) star_direct_kernel(StarArgs a, int64_t nw
         float v = c0 * w[4 + e];
 #pragma unroll
         for (int k = 1; k <= R; ++k) {
-            const float yv = (&yu[k - 1].x)[e], ydv = (&yd[k - 1].x)[e];
-            const float zv = (&zu[k - 1].x)[e], zdv = (&zd[k - 1].x)[e];
+            const float yv = at(yu[k - 1], e), ydv = at(yd[k - 1], e);
+            const float zv = at(zu[k - 1], e), zdv = at(zd[k - 1], e);
             v = fmaf(a.c[2][R + k], w[4 + e + k], v);
             v = fmaf(a.c[2][R - k], w[4 + e - k], v);
             v = fmaf(a.c[1][R + k], yv, v);
